@@ -1,0 +1,46 @@
+"""Stored reference spectra (written by tests/golden/make_golden.py from the oracle).
+
+Checks that the files are consistent with the paper's structure (the merged block
+spectrum is the full spectrum) and that the oracle still reproduces them.
+"""
+
+import json
+import os
+
+import numpy as np
+
+from oracle import eigen as E
+from synth import two_phase_cell
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def test_n8_golden_block_union():
+    g = _load("two_phase_n8.json")
+    for pt in g["points"].values():
+        full = np.array(pt["full_lowest"])
+        merged = np.sort(np.concatenate([np.array(b) for b in pt["block_lowest"]]))[:full.size]
+        assert np.abs(full - merged).max() <= 1e-12 * full.max()
+
+
+def test_n8_golden_reproduces():
+    g = _load("two_phase_n8.json")
+    dims = tuple(g["dims"])
+    C21, rho, _ = two_phase_cell(dims, radius=g["radius"], seed=g["seed"])
+    pt = g["points"]["k"]
+    ev = E.block_spectrum(dims, pt["kappa"], C21, rho, 1)[:12]
+    assert np.allclose(ev, pt["block_lowest"][1], rtol=1e-12, atol=0)
+
+
+def test_n16_golden_one_block_dense():
+    """The ARPACK values of one n=16 block agree with dense eigh of that block."""
+    g = _load("two_phase_n16.json")
+    dims = tuple(g["dims"])
+    C21, rho, _ = two_phase_cell(dims, radius=g["radius"], seed=g["seed"])
+    ev = E.block_spectrum(dims, g["kappa"], C21, rho, 2)[:10]
+    assert np.allclose(ev, g["block_lowest"][2], rtol=1e-10, atol=0)
