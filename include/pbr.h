@@ -1,0 +1,201 @@
+/*
+ * pbr.h -- C interface of libpbr, a GPU (MI355X, gfx950) implementation of the
+ * parity-blocked rotated staggered discretisation of the Bloch elastic
+ * eigenproblem
+ *
+ *     A_h(k) v = omega^2 M_h v,     A_h(k) = B_h(k) C_h B_h(k)^H
+ *
+ * (Sec. 3.3, Eq. 3.15).  B_h is assembled from four Bloch-periodic
+ * body-diagonal differences (Eqs. 3.9-3.14), C_h is the nodewise 6x6 Voigt
+ * stiffness (order [11,22,33,23,13,12], engineering shear; Sec. 2, Eq. 2.6) and
+ * M_h = I_3 (x) diag(rho).  On even grids the problem splits into four parity
+ * blocks (Theorem 4.1, Corollary 4.2); the library applies the operator, its
+ * FFT-diagonal preconditioner, the shift-invert inner solve and the outer
+ * Krylov eigensolver either in the full space or per block.
+ *
+ * CONVENTIONS (all calls)
+ *   Grid        n1 x n2 x n3 nodes, node (i,j,k) has natural index
+ *               i + n1*(j + n2*k) (i fastest; the Kronecker order of Eq. 3.5).
+ *               Reduced spacings h_s = 1/n_s.
+ *   Bloch k     kappa[3] in reduced reciprocal coordinates; boundary phases
+ *               phi_l = 2*pi*kappa_l (Sec. 3.1, Eq. 3.3).
+ *   Vectors     complex128, interleaved (re, im), component-major
+ *               [v1 | v2 | v3]; each component has one entry per node.
+ *   Blocks      block = -1 is the full space (3n unknowns); block = b in 0..3
+ *               selects the parity block b = 2a + c, a = (i+j) mod 2,
+ *               c = (j+k) mod 2, i.e. the paper's (sigma12, sigma13) =
+ *               ((-1)^a, (-1)^(a+c)) (Sec. 4, Eqs. 4.2 and 4.11).  A block
+ *               vector has 3n/4 entries; its node t = i + n1*(y2 + (n2/2)*y3)
+ *               is the grid node (i, 2*y2 + o2, 2*y3 + o3) with
+ *               o2 = (a+i) mod 2, o3 = (a+c+i) mod 2.  Blocks need even n1,n2,n3.
+ *   Material    C21: n x 21 row-major doubles, per node the upper triangle of
+ *               the symmetric Voigt matrix row by row (C11..C16, C22..C26, ...,
+ *               C66), natural node order; rho: n doubles, all > 0.
+ *   Lattice     A_lat: 3x3 column-major [a1|a2|a3] (NULL = identity); the
+ *               Cartesian derivatives are D_m = sum_s (A_lat^-1)_{sm} Dhat_s
+ *               (Sec. 3.3, Eq. 3.13).
+ *   Eigenvalues lambda = omega^2, ascending.  f = sqrt(lambda)/(2 pi) is the
+ *               caller's business.
+ *
+ * MEMORY AND STREAMS
+ *   The caller owns every pointer it passes.  With on_device = 0 pointers are
+ *   host memory, read or written before the call returns.  With on_device = 1
+ *   they are device memory on the context's device, and the work is ordered on
+ *   the context's stream (the caller synchronises before reading results; the
+ *   library does not synchronise the stream except where a call must read a
+ *   device scalar on the host, which the descriptions below say).  The context
+ *   owns its device copies of the material and all work buffers; pbr_destroy
+ *   frees them.
+ *
+ * ERRORS
+ *   Every call returns a pbr_status and never throws.  A human-readable
+ *   message for the last failing call on a context is returned by
+ *   pbr_last_error(ctx) (pbr_last_error(NULL) for pbr_create failures).
+ */
+#ifndef PBR_H
+#define PBR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbr_ctx pbr_ctx;
+
+typedef enum pbr_status {
+  PBR_OK = 0,
+  PBR_EINVAL = -1,    /* bad argument: sizes, NaN/Inf or non-positive rho, nev, ... */
+  PBR_EODDGRID = -2,  /* block >= 0 on a grid with an odd n_l (Theorem 4.1 needs even) */
+  PBR_ENOMEM = -3,    /* device or host allocation failed */
+  PBR_EDEVICE = -4,   /* a HIP runtime call failed */
+  PBR_ENOCONV = -5,   /* iteration limit reached; partial results are written */
+  PBR_ESTATE = -6     /* call made before pbr_set_material */
+} pbr_status;
+
+/* Solver settings (Sec. 7.1: tolerances 1e-12, 300 outer / 200 inner iterations). */
+typedef struct pbr_opts {
+  double tol;        /* outer: Ritz residual <= tol * |mu| of the shift-invert operator */
+  double tol_inner;  /* inner PCG: ||r|| <= tol_inner * ||b|| (2-norm) */
+  int maxit_outer;   /* maximum Krylov restarts */
+  int maxit_inner;   /* maximum PCG iterations per solve */
+  int ncv;           /* Krylov basis size; 0 = automatic (2*nev + 10, at most dim) */
+  int precond;       /* 1 = FFT-diagonal preconditioner, 0 = none */
+  int check_every;   /* PCG iterations between host convergence checks; 0 = automatic */
+  int seed;          /* seed of the (deterministic) start vector */
+} pbr_opts;
+
+/* Statistics of one pbr_solve / pbr_eigs / pbr_eigs_merged / pbr_band_path call. */
+typedef struct pbr_stats {
+  int outer_iters;      /* Krylov restarts */
+  int op_applies;       /* shift-invert applications (one PCG solve each) */
+  int pcg_iters_total;  /* sum of PCG iterations */
+  int pcg_iters_max;    /* largest PCG iteration count of one solve */
+  int matvecs;          /* applications of A_h + s M_h (including final checks) */
+  int n_zero;           /* Gamma null modes removed: 12 full space, 3 per block, else 0 */
+  int converged;        /* eigenpairs (or 1 for a converged solve) delivered */
+  int nev_block[4];     /* per-block nev used by pbr_eigs_merged (last k-point) */
+  double pcg_avg;       /* pcg_iters_total / op_applies */
+  double max_rel_resid; /* max ||A v - lambda M v|| / (||A v|| + |lambda| ||M v||) */
+  double seconds;       /* host wall time of the call */
+} pbr_stats;
+
+/* Fill *o with the defaults: tol 1e-12, tol_inner 1e-12, maxit 300 / 200,
+ * ncv automatic, precond 1, check_every automatic, seed 1. */
+void pbr_opts_default(pbr_opts *o);
+
+/* Create a context for an n1 x n2 x n3 grid on HIP device `hip_device`.
+ * hip_stream: a hipStream_t to order all work on, or NULL for a context-owned
+ * stream.  A_lat: see CONVENTIONS.  Fails with PBR_EINVAL for n_l < 1 or a
+ * singular A_lat, PBR_EDEVICE if the device cannot be used. */
+pbr_status pbr_create(pbr_ctx **out, int n1, int n2, int n3, const double *A_lat,
+                      int hip_device, void *hip_stream);
+
+/* Upload the stiffness and density fields (layout in CONVENTIONS) and build the
+ * per-block copies.  The preconditioner reference is reset to the volume means
+ * of C and rho.  Fails with PBR_EINVAL on NaN/Inf entries or rho <= 0 (the check
+ * reads the data on the host; device inputs are copied back for it). */
+pbr_status pbr_set_material(pbr_ctx *c, const double *C21, const double *rho,
+                            int on_device);
+
+/* Override the constant reference material of the preconditioner
+ * (K(m) = Bhat(m) C_ref Bhat(m)^H + shift * rho_ref * I_3, Sec. 5.3-5.4): C21_ref
+ * is 21 host doubles in the C21 order, rho_ref > 0. */
+pbr_status pbr_set_reference(pbr_ctx *c, const double *C21_ref, double rho_ref);
+
+/* delta = 0.30 * C_max, C_max the largest |C_pq| of the material (Eq. 7.7).
+ * Returns a negative value before pbr_set_material. */
+double pbr_default_shift(const pbr_ctx *c);
+
+/* Number of complex unknowns: 3n for block = -1, 3n/4 for a block; -1 on
+ * error (bad block or odd grid). */
+long pbr_block_dim(const pbr_ctx *c, int block);
+
+/* y = Q_b^* full (gather) and full = Q_b y on block b's entries (scatter; the
+ * other entries of full are left untouched) -- Corollary 4.2, Eq. 4.14. */
+pbr_status pbr_block_gather(pbr_ctx *c, int block, const void *full, void *blk,
+                            int on_device);
+pbr_status pbr_block_scatter(pbr_ctx *c, int block, const void *blk, void *full,
+                             int on_device);
+
+/* y = (A_h(k) + s M_h) x in the full space (block = -1) or restricted to a
+ * parity block (A_sigma + s M_sigma, Eq. 4.14), matrix-free as
+ * x -> B^H x -> C B^H x -> B C B^H x (Sec. 6.1).  x and y must not overlap. */
+pbr_status pbr_apply(pbr_ctx *c, const double kappa[3], int block, double s,
+                     const void *x, void *y, int on_device);
+
+/* z = T_xi diag_m(K(m)^-1) T_xi^H r with K(m) = Bhat(m) C_ref Bhat(m)^H +
+ * shift * rho_ref * I_3: the FFT-diagonal preconditioner of the shifted system
+ * (Fourier bases of Sec. 5.1-5.2, symbols Eqs. 5.8-5.11; T_xi = T full,
+ * T_sigma = T F_sigma for a block).  shift > 0. */
+pbr_status pbr_precond(pbr_ctx *c, const double kappa[3], int block, double shift,
+                       const void *r, void *z, int on_device);
+
+/* Solve (A_h(k) + shift M_h) x = b (block: A_sigma, M_sigma) by preconditioned
+ * conjugate gradients from x = 0 (the inner solve of Sec. 6.1, Eq. 6.2).  Reads
+ * the residual norm on the host every opts->check_every iterations.  Returns
+ * PBR_ENOCONV (x holds the last iterate) if opts->maxit_inner is reached. */
+pbr_status pbr_solve(pbr_ctx *c, const double kappa[3], int block, double shift,
+                     const void *b, void *x, const pbr_opts *opts, pbr_stats *st,
+                     int on_device);
+
+/* nev lowest eigenvalues of (A_h(k), M_h) (block = -1) or of block b
+ * (Corollary 4.2), by a thick-restart Lanczos (Krylov-Schur) iteration on the
+ * shift-invert operator (A + shift M)^-1 M (Sec. 6.1), each application being a
+ * pbr_solve.  shift <= 0 selects pbr_default_shift.  At the Gamma point (every
+ * kappa_l an integer) the zero-derivative modes chi_mu e_alpha (Sec. 6.2,
+ * Appendix C) are projected out and the nev lowest non-zero eigenvalues are
+ * returned; st->n_zero reports how many null modes were removed.
+ * evals: nev host doubles.  evecs: NULL, or dim x nev complex128 column-major
+ * (on the host if evecs_on_device = 0), M-normalised (v^H M v = 1).
+ * Fails with PBR_EINVAL if nev < 1 or nev + n_zero >= dim. */
+pbr_status pbr_eigs(pbr_ctx *c, const double kappa[3], int block, int nev,
+                    double shift, const pbr_opts *opts, double *evals, void *evecs,
+                    int evecs_on_device, pbr_stats *st);
+
+/* nev lowest eigenvalues of the full pencil obtained by solving the four parity
+ * blocks and merging their spectra (Sec. 6.1).  Each block starts with
+ * nev_b = ceil(nev/4) + 4 eigenpairs; a block whose largest computed eigenvalue
+ * lies below the merged nev-th value is recomputed with more eigenpairs until
+ * every block certifies the cut.  Needs an even grid. */
+pbr_status pbr_eigs_merged(pbr_ctx *c, const double kappa[3], int nev, double shift,
+                           const pbr_opts *opts, double *evals, pbr_stats *st);
+
+/* Band structure along nk reduced wave vectors kappas (nk x 3 row-major host
+ * doubles): evals[q*nev + t] is the t-th eigenvalue at kappa q.  blocked = 1
+ * uses pbr_eigs_merged at every point, blocked = 0 the full-space pbr_eigs.
+ * st (optional) accumulates over the path. */
+pbr_status pbr_band_path(pbr_ctx *c, int nk, const double *kappas, int nev,
+                         int blocked, double shift, const pbr_opts *opts,
+                         double *evals, pbr_stats *st);
+
+/* Message of the last failing call on c (or of the last failing pbr_create when
+ * c is NULL).  The string lives until the next call on c. */
+const char *pbr_last_error(const pbr_ctx *c);
+
+/* Free the context and all its device memory.  NULL is ignored. */
+void pbr_destroy(pbr_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBR_H */

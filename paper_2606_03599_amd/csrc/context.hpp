@@ -1,0 +1,100 @@
+// Context of libpbr: grid, material on the device (natural layout and the four
+// parity-block layouts), per-layout work buffers and the kernel entry points
+// used by the solver drivers.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/pbr.h"
+#include "common.hpp"
+#include "geometry.hpp"
+
+// Device material in one layout: C as 21 planes of N doubles (SoA), rho, sqrt(rho).
+struct DevMaterial {
+  long N = 0;
+  double* C = nullptr;      // [21][N]
+  double* rho = nullptr;    // [N]
+  double* srho = nullptr;   // [N]  sqrt(rho)
+  double* isrho = nullptr;  // [N]  1/sqrt(rho)
+};
+
+// Per-kappa tables of the FFT preconditioner for one layout.
+struct FftTables {
+  double kappa[3] = {1e300, 1e300, 1e300};
+  cplx* twist[3] = {nullptr, nullptr, nullptr};   // e^{-i x phi_l / L_l}, x in [0,L_l)
+  cplx* post[3] = {nullptr, nullptr, nullptr};    // e^{-i beta_q} per frequency (block y2/y3)
+  cplx* roots[3] = {nullptr, nullptr, nullptr};   // e^{-2 pi i k / L_l}
+  int L[3] = {0, 0, 0};
+};
+
+struct PcgScalars;
+
+// Work buffers of one layout (allocated on first use).
+struct LayoutWork {
+  long N = 0;                 // nodes
+  cplx *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+  cplx *b = nullptr, *w = nullptr, *t = nullptr;   // Lanczos / staging vectors
+  cplx *U = nullptr, *U2 = nullptr;                // Krylov bases (3N x ucols)
+  int ucols = 0;
+  cplx* small = nullptr;      // small device matrices (h, Y), 4096 complex
+  double* part = nullptr;     // reduction partials
+  double* part2 = nullptr;
+  double* dscal = nullptr;    // small device scalars (256 doubles)
+  PcgScalars* st = nullptr;
+  double* Wnull = nullptr;    // Gamma null fields (nf x N real, orthonormal after sqrt(rho))
+  int nf = 0;
+};
+
+struct pbr_ctx {
+  int n1 = 0, n2 = 0, n3 = 0;
+  long n = 0;
+  bool even = false;
+  double Alat[9];      // column-major
+  double Ainv[9];      // row-major: Ainv[s*3+m] = (A_lat^-1)_{sm}
+  double cf[3][5];     // Cartesian stencil coefficients
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  bool have_material = false;
+  double Cmax = 0.0;
+  double Cref[21];
+  double rho_ref = 1.0;
+  std::vector<double> rho_host;   // natural order
+  DevMaterial mat[5];  // index 0 = natural (full), 1..4 = blocks 0..3
+  FftTables fft[5];
+  LayoutWork work[5];
+
+  double* hpinned = nullptr;      // pinned host scratch (4096 doubles)
+
+  std::string err;
+  void set_error(const std::string& s) { err = s; }
+
+  DevMaterial& material(int block) { return mat[block + 1]; }
+  long layout_nodes(int block) const { return block < 0 ? n : n / 4; }
+};
+
+// ---- kernels / device helpers (implemented in the .hip files) ----
+int dev_alloc(pbr_ctx* c, void** p, size_t bytes);
+void dev_free(void* p);
+int upload_material(pbr_ctx* c, const double* C21_host, const double* rho_host);
+int layout_gather(pbr_ctx* c, int block, const cplx* full, cplx* blk);
+int layout_scatter(pbr_ctx* c, int block, const cplx* blk, cplx* full);
+
+// Geometry of a layout at wave vector kappa.
+Geo make_geo(const pbr_ctx* c, int block, const double kappa[3]);
+// y = (A + s M) x in layout `block`
+int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y);
+// z = preconditioner(r) in layout `block`
+int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
+                   const cplx* r, cplx* z);
+
+// solver drivers (solver.cpp)
+int ensure_work(pbr_ctx* c, int block);
+int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b, cplx* x,
+              const pbr_opts& o, int* iters, int* conv);
+int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double shift,
+                 const pbr_opts& o, double* evals, cplx* evecs_dev, pbr_stats* st);
+int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const pbr_opts& o,
+                double* evals, pbr_stats* st);

@@ -1,0 +1,148 @@
+// Layout kernels: material upload into the natural and parity-block layouts,
+// and the gather / scatter maps Q_b^* and Q_b between a full vector and a block
+// vector (Corollary 4.2, Eq. 4.14).  Block position t = i + n1*(y2 + m2*y3) is
+// the node (i, 2*y2 + (a+i)%2, 2*y3 + (a+c+i)%2).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "context.hpp"
+
+namespace {
+
+__device__ inline long block_to_natural(int n1, int n2, int m2, int a, int c, long t) {
+  const int i = (int)(t % n1);
+  const long r = t / n1;
+  const int y2 = (int)(r % m2);
+  const int y3 = (int)(r / m2);
+  const int j = 2 * y2 + ((a + i) & 1);
+  const int k = 2 * y3 + ((a + c + i) & 1);
+  return (long)i + (long)n1 * ((long)j + (long)n2 * k);
+}
+
+struct MapArgs {
+  int n1, n2, n3, m2, a, c;
+  long nb, n;
+};
+
+__global__ void gather_kernel(MapArgs m, const cplx* __restrict__ full, cplx* __restrict__ blk) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.nb) return;
+  const long x = block_to_natural(m.n1, m.n2, m.m2, m.a, m.c, t);
+  for (int a = 0; a < 3; ++a) blk[a * m.nb + t] = full[a * m.n + x];
+}
+
+__global__ void scatter_kernel(MapArgs m, const cplx* __restrict__ blk, cplx* __restrict__ full) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.nb) return;
+  const long x = block_to_natural(m.n1, m.n2, m.m2, m.a, m.c, t);
+  for (int a = 0; a < 3; ++a) full[a * m.n + x] = blk[a * m.nb + t];
+}
+
+// Repack one material plane set (nplanes planes of n doubles) into block order.
+__global__ void repack_kernel(MapArgs m, int nplanes, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.nb) return;
+  const long x = block_to_natural(m.n1, m.n2, m.m2, m.a, m.c, t);
+  for (int q = 0; q < nplanes; ++q) dst[q * m.nb + t] = src[q * m.n + x];
+}
+
+__global__ void sqrt_kernel(long N, const double* __restrict__ rho, double* __restrict__ s,
+                            double* __restrict__ is) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double r = sqrt(rho[t]);
+  s[t] = r;
+  is[t] = 1.0 / r;
+}
+
+MapArgs map_args(const pbr_ctx* c, int block) {
+  MapArgs m;
+  m.n1 = c->n1;
+  m.n2 = c->n2;
+  m.n3 = c->n3;
+  m.m2 = c->n2 / 2;
+  m.a = block >> 1;
+  m.c = block & 1;
+  m.n = c->n;
+  m.nb = c->n / 4;
+  return m;
+}
+
+int alloc_material(pbr_ctx* c, DevMaterial& M, long N) {
+  if (M.N == N && M.C) return ST_OK;
+  M.N = N;
+  PBR_TRY(dev_alloc(c, (void**)&M.C, sizeof(double) * 21 * N));
+  PBR_TRY(dev_alloc(c, (void**)&M.rho, sizeof(double) * N));
+  PBR_TRY(dev_alloc(c, (void**)&M.srho, sizeof(double) * N));
+  PBR_TRY(dev_alloc(c, (void**)&M.isrho, sizeof(double) * N));
+  return ST_OK;
+}
+
+}  // namespace
+
+int dev_alloc(pbr_ctx* c, void** p, size_t bytes) {
+  if (*p) return ST_OK;
+  hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 16);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    c->set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    return ST_ENOMEM;
+  }
+  return ST_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
+  const long n = c->n;
+  // host transpose to 21 planes
+  std::vector<double> planes((size_t)21 * n);
+  for (long x = 0; x < n; ++x)
+    for (int q = 0; q < 21; ++q) planes[(size_t)q * n + x] = C21[(size_t)x * 21 + q];
+  DevMaterial& F = c->mat[0];
+  PBR_TRY(alloc_material(c, F, n));
+  PBR_HIP(c, hipMemcpyAsync(F.C, planes.data(), sizeof(double) * 21 * n, hipMemcpyHostToDevice,
+                            c->stream));
+  PBR_HIP(c, hipMemcpyAsync(F.rho, rho, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(sqrt_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream, n, F.rho,
+                     F.srho, F.isrho);
+  PBR_HIP(c, hipGetLastError());
+  if (c->even) {
+    for (int b = 0; b < 4; ++b) {
+      DevMaterial& B = c->mat[b + 1];
+      const long nb = n / 4;
+      PBR_TRY(alloc_material(c, B, nb));
+      MapArgs m = map_args(c, b);
+      hipLaunchKernelGGL(repack_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, m, 21,
+                         (const double*)F.C, B.C);
+      hipLaunchKernelGGL(repack_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, m, 1,
+                         (const double*)F.rho, B.rho);
+      hipLaunchKernelGGL(sqrt_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, nb, B.rho,
+                         B.srho, B.isrho);
+      PBR_HIP(c, hipGetLastError());
+    }
+  }
+  // the host staging vector dies at return: wait for the copies
+  PBR_HIP(c, hipStreamSynchronize(c->stream));
+  return ST_OK;
+}
+
+int layout_gather(pbr_ctx* c, int block, const cplx* full, cplx* blk) {
+  MapArgs m = map_args(c, block);
+  hipLaunchKernelGGL(gather_kernel, dim3(ceil_div(m.nb, 256)), dim3(256), 0, c->stream, m, full,
+                     blk);
+  PBR_HIP(c, hipGetLastError());
+  return ST_OK;
+}
+
+int layout_scatter(pbr_ctx* c, int block, const cplx* blk, cplx* full) {
+  MapArgs m = map_args(c, block);
+  hipLaunchKernelGGL(scatter_kernel, dim3(ceil_div(m.nb, 256)), dim3(256), 0, c->stream, m, blk,
+                     full);
+  PBR_HIP(c, hipGetLastError());
+  return ST_OK;
+}

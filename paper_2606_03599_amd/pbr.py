@@ -1,0 +1,363 @@
+"""Python binding of libpbr (include/pbr.h): argument marshalling only.
+
+Every function has the name of the C entry point it wraps and forwards to it
+through ctypes; all computation happens in the HIP library.  Vectors may be
+
+* torch tensors on the context's GPU (complex128, contiguous): passed by device
+  pointer with on_device = 1 and ordered on the context stream;
+* numpy arrays (complex128 / float64, C-contiguous): passed by host pointer with
+  on_device = 0.
+
+If libpbr.so is missing the import fails loudly: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbr.so")
+
+PBR_OK, PBR_EINVAL, PBR_EODDGRID, PBR_ENOMEM, PBR_EDEVICE, PBR_ENOCONV, PBR_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6)
+STATUS_NAMES = {0: "PBR_OK", -1: "PBR_EINVAL", -2: "PBR_EODDGRID", -3: "PBR_ENOMEM",
+                -4: "PBR_EDEVICE", -5: "PBR_ENOCONV", -6: "PBR_ESTATE"}
+
+
+class PbrOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("tol_inner", ctypes.c_double),
+                ("maxit_outer", ctypes.c_int), ("maxit_inner", ctypes.c_int),
+                ("ncv", ctypes.c_int), ("precond", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("seed", ctypes.c_int)]
+
+
+class PbrStats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("op_applies", ctypes.c_int),
+                ("pcg_iters_total", ctypes.c_int), ("pcg_iters_max", ctypes.c_int),
+                ("matvecs", ctypes.c_int), ("n_zero", ctypes.c_int),
+                ("converged", ctypes.c_int), ("nev_block", ctypes.c_int * 4),
+                ("pcg_avg", ctypes.c_double), ("max_rel_resid", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["nev_block"] = list(self.nev_block)
+        return d
+
+
+class PbrError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_SIGS = {
+    "pbr_opts_default": (None, [ctypes.POINTER(PbrOpts)]),
+    "pbr_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  _dp, ctypes.c_int, _vp]),
+    "pbr_set_material": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "pbr_set_reference": (ctypes.c_int, [_vp, _dp, ctypes.c_double]),
+    "pbr_default_shift": (ctypes.c_double, [_vp]),
+    "pbr_block_dim": (ctypes.c_long, [_vp, ctypes.c_int]),
+    "pbr_block_gather": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]),
+    "pbr_block_scatter": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]),
+    "pbr_apply": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
+                                 ctypes.c_int]),
+    "pbr_precond": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
+                                   ctypes.c_int]),
+    "pbr_solve": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
+                                 ctypes.POINTER(PbrOpts), ctypes.POINTER(PbrStats),
+                                 ctypes.c_int]),
+    "pbr_eigs": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.POINTER(PbrOpts), _dp, _vp, ctypes.c_int,
+                                ctypes.POINTER(PbrStats)]),
+    "pbr_eigs_merged": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double,
+                                       ctypes.POINTER(PbrOpts), _dp,
+                                       ctypes.POINTER(PbrStats)]),
+    "pbr_band_path": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.POINTER(PbrOpts), _dp,
+                                     ctypes.POINTER(PbrStats)]),
+    "pbr_last_error": (ctypes.c_char_p, [_vp]),
+    "pbr_destroy": (None, [_vp]),
+    "pbr_host_heev": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp]),
+    "pbr_host_merge": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(_dp), _dp]),
+}
+
+
+def lib():
+    """Load libpbr.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "python -m paper_2606_03599_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status):
+    if status != PBR_OK:
+        msg = lib().pbr_last_error(ctx)
+        raise PbrError(status, msg.decode() if msg else "")
+    return status
+
+
+def _is_torch(x):
+    return type(x).__module__.split(".")[0] == "torch"
+
+
+def _vec(x, dtype=np.complex128):
+    """(pointer, on_device, keepalive) of a vector argument."""
+    if _is_torch(x):
+        import torch
+        want = torch.complex128 if dtype == np.complex128 else torch.float64
+        if x.dtype != want or not x.is_contiguous():
+            raise TypeError(f"expected a contiguous {want} tensor")
+        if x.device.type != "cuda":
+            raise TypeError("torch tensors must live on the GPU; pass numpy arrays for host data")
+        return x.data_ptr(), 1, x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data, 0, a
+
+
+def _same_place(*ons):
+    if len(set(ons)) != 1:
+        raise TypeError("mix of device tensors and host arrays in one call")
+    return ons[0]
+
+
+def _kappa(kappa):
+    k = (ctypes.c_double * 3)(*[float(v) for v in kappa])
+    return ctypes.cast(k, _dp), k
+
+
+def pbr_opts_default() -> PbrOpts:
+    o = PbrOpts()
+    lib().pbr_opts_default(ctypes.byref(o))
+    return o
+
+
+def pbr_create(n1, n2, n3, A_lat=None, device=0, stream=None):
+    """Returns an opaque context handle (int)."""
+    h = _vp()
+    keep = None
+    if A_lat is None:
+        ap = None
+    else:
+        keep = np.asfortranarray(np.asarray(A_lat, dtype=np.float64).reshape(3, 3)).ravel(order="F")
+        keep = np.ascontiguousarray(keep)
+        ap = keep.ctypes.data_as(_dp)
+    st = lib().pbr_create(ctypes.byref(h), int(n1), int(n2), int(n3), ap, int(device),
+                          _vp(stream) if stream else None)
+    _check(None, st)
+    return h.value
+
+
+def pbr_destroy(ctx):
+    lib().pbr_destroy(ctx)
+
+
+def pbr_last_error(ctx):
+    m = lib().pbr_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def pbr_set_material(ctx, C21, rho):
+    pc, oc, kc = _vec(C21, np.float64)
+    pr, orr, kr = _vec(rho, np.float64)
+    _check(ctx, lib().pbr_set_material(ctx, pc, pr, _same_place(oc, orr)))
+
+
+def pbr_set_reference(ctx, C21_ref, rho_ref):
+    a = np.ascontiguousarray(np.asarray(C21_ref, dtype=np.float64).reshape(21))
+    _check(ctx, lib().pbr_set_reference(ctx, a.ctypes.data_as(_dp), float(rho_ref)))
+
+
+def pbr_default_shift(ctx):
+    return lib().pbr_default_shift(ctx)
+
+
+def pbr_block_dim(ctx, block):
+    return int(lib().pbr_block_dim(ctx, int(block)))
+
+
+def pbr_block_gather(ctx, block, full, blk):
+    pf, of, kf = _vec(full)
+    pb, ob, kb = _vec(blk)
+    _check(ctx, lib().pbr_block_gather(ctx, int(block), pf, pb, _same_place(of, ob)))
+    return kb
+
+
+def pbr_block_scatter(ctx, block, blk, full):
+    pb, ob, kb = _vec(blk)
+    pf, of, kf = _vec(full)
+    _check(ctx, lib().pbr_block_scatter(ctx, int(block), pb, pf, _same_place(ob, of)))
+    return kf
+
+
+def pbr_apply(ctx, kappa, block, s, x, y):
+    kp, kk = _kappa(kappa)
+    px, ox, kx = _vec(x)
+    py, oy, ky = _vec(y)
+    _check(ctx, lib().pbr_apply(ctx, kp, int(block), float(s), px, py, _same_place(ox, oy)))
+    return ky
+
+
+def pbr_precond(ctx, kappa, block, shift, r, z):
+    kp, kk = _kappa(kappa)
+    pr, orr, kr = _vec(r)
+    pz, oz, kz = _vec(z)
+    _check(ctx, lib().pbr_precond(ctx, kp, int(block), float(shift), pr, pz,
+                                  _same_place(orr, oz)))
+    return kz
+
+
+def pbr_solve(ctx, kappa, block, shift, b, x, opts=None, raise_on_noconv=True):
+    kp, kk = _kappa(kappa)
+    pb, ob, kb = _vec(b)
+    px, ox, kx = _vec(x)
+    st = PbrStats()
+    o = opts if opts is not None else pbr_opts_default()
+    status = lib().pbr_solve(ctx, kp, int(block), float(shift), pb, px, ctypes.byref(o),
+                             ctypes.byref(st), _same_place(ob, ox))
+    if status != PBR_ENOCONV or raise_on_noconv:
+        _check(ctx, status)
+    return kx, st
+
+
+def pbr_eigs(ctx, kappa, block, nev, shift=0.0, opts=None, evecs=None, raise_on_noconv=True):
+    """Returns (evals numpy (nev,), stats, evecs or None)."""
+    kp, kk = _kappa(kappa)
+    ev = np.zeros(int(nev))
+    st = PbrStats()
+    o = opts if opts is not None else pbr_opts_default()
+    pe, oe, ke = (None, 0, None) if evecs is None else _vec(evecs)
+    status = lib().pbr_eigs(ctx, kp, int(block), int(nev), float(shift), ctypes.byref(o),
+                            ev.ctypes.data_as(_dp), pe, oe, ctypes.byref(st))
+    if status != PBR_ENOCONV or raise_on_noconv:
+        _check(ctx, status)
+    return ev, st, ke
+
+
+def pbr_eigs_merged(ctx, kappa, nev, shift=0.0, opts=None, raise_on_noconv=True):
+    kp, kk = _kappa(kappa)
+    ev = np.zeros(int(nev))
+    st = PbrStats()
+    o = opts if opts is not None else pbr_opts_default()
+    status = lib().pbr_eigs_merged(ctx, kp, int(nev), float(shift), ctypes.byref(o),
+                                   ev.ctypes.data_as(_dp), ctypes.byref(st))
+    if status != PBR_ENOCONV or raise_on_noconv:
+        _check(ctx, status)
+    return ev, st
+
+
+def pbr_band_path(ctx, kappas, nev, blocked=True, shift=0.0, opts=None, raise_on_noconv=True):
+    ks = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64).reshape(-1, 3))
+    ev = np.zeros((ks.shape[0], int(nev)))
+    st = PbrStats()
+    o = opts if opts is not None else pbr_opts_default()
+    status = lib().pbr_band_path(ctx, ks.shape[0], ks.ctypes.data_as(_dp), int(nev),
+                                 1 if blocked else 0, float(shift), ctypes.byref(o),
+                                 ev.ctypes.data_as(_dp), ctypes.byref(st))
+    if status != PBR_ENOCONV or raise_on_noconv:
+        _check(ctx, status)
+    return ev, st
+
+
+def pbr_host_heev(A):
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128).T)  # column-major
+    m = A.shape[0]
+    w = np.zeros(m)
+    V = np.zeros((m, m), dtype=np.complex128)
+    st = lib().pbr_host_heev(m, A.ctypes.data_as(_dp), w.ctypes.data_as(_dp),
+                             V.ctypes.data_as(_dp))
+    if st != 0:
+        raise PbrError(st, "pbr_host_heev failed")
+    return w, np.ascontiguousarray(V.T)
+
+
+def pbr_host_merge(nev, block_vals):
+    nb = (ctypes.c_int * 4)(*[len(v) for v in block_vals])
+    arrs = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in block_vals]
+    ptrs = (_dp * 4)(*[a.ctypes.data_as(_dp) for a in arrs])
+    out = np.zeros(int(nev))
+    mask = lib().pbr_host_merge(int(nev), nb, ptrs, out.ctypes.data_as(_dp))
+    return mask, out
+
+
+class Context:
+    """Owning wrapper around a pbr_ctx handle (methods forward to the pbr_* calls)."""
+
+    def __init__(self, dims, A_lat=None, device=0, stream=None):
+        if isinstance(dims, int):
+            dims = (dims, dims, dims)
+        self.dims = tuple(int(d) for d in dims)
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:
+                stream = None
+        self.h = pbr_create(*self.dims, A_lat=A_lat, device=device, stream=stream)
+
+    def close(self):
+        if self.h:
+            pbr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_material(self, C21, rho):
+        pbr_set_material(self.h, C21, rho)
+
+    def set_reference(self, C21_ref, rho_ref):
+        pbr_set_reference(self.h, C21_ref, rho_ref)
+
+    def default_shift(self):
+        return pbr_default_shift(self.h)
+
+    def block_dim(self, block):
+        return pbr_block_dim(self.h, block)
+
+    def apply(self, kappa, block, s, x, y):
+        return pbr_apply(self.h, kappa, block, s, x, y)
+
+    def precond(self, kappa, block, shift, r, z):
+        return pbr_precond(self.h, kappa, block, shift, r, z)
+
+    def solve(self, kappa, block, shift, b, x, opts=None):
+        return pbr_solve(self.h, kappa, block, shift, b, x, opts)
+
+    def eigs(self, kappa, block, nev, shift=0.0, opts=None, evecs=None):
+        return pbr_eigs(self.h, kappa, block, nev, shift, opts, evecs)
+
+    def eigs_merged(self, kappa, nev, shift=0.0, opts=None):
+        return pbr_eigs_merged(self.h, kappa, nev, shift, opts)
+
+    def band_path(self, kappas, nev, blocked=True, shift=0.0, opts=None):
+        return pbr_band_path(self.h, kappas, nev, blocked, shift, opts)
+
+    def gather(self, block, full, blk):
+        return pbr_block_gather(self.h, block, full, blk)
+
+    def scatter(self, block, blk, full):
+        return pbr_block_scatter(self.h, block, blk, full)

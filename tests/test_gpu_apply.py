@@ -1,0 +1,134 @@
+"""GPU matvec y = (A_h(k) + s M_h) x through pbr_apply vs the oracle.
+
+Tolerance: 1e-12 relative in the 2-norm on seeded complex-Gaussian x (the
+matvec parity target).  Small grids sweep every output against the Kronecker /
+index-formula oracle; n = 64 is compared in full against the vectorised index
+formula; n = 128 (the benchmark size, same launch configuration) is compared on
+sampled output nodes computed one by one.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import blocks as Bk, discretization as D, pointwise as P
+from synth import complex_gaussian, random_spd_field, two_phase_cell
+
+from gpu_util import log, make_ctx, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = (0.15, 0.05, 0.10)
+FCC = 0.5 * np.array([[0, 1, 1], [1, 0, 1], [1, 1, 0]], dtype=float)
+TOL = 1e-12
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (4, 4, 4), (8, 8, 8), (4, 6, 2), (6, 4, 10)])
+@pytest.mark.parametrize("A_lat", [None, "fcc"])
+def test_apply_small_full_and_blocks(dims, A_lat):
+    Al = FCC if A_lat == "fcc" else None
+    log(f"apply dims={dims} A_lat={A_lat}")
+    C21, rho = random_spd_field(dims, seed=3)
+    n = int(np.prod(dims))
+    ctx = make_ctx(dims, C21, rho, Al)
+    for kap in (KAPPA, (0.0, 0.0, 0.0), (0.5, -0.25, 1.0)):
+        A = D.assemble_A(dims, kap, C21, Al)
+        M = D.assemble_M(rho)
+        x = complex_gaussian(3 * n, seed=12345)
+        s = 0.7
+        y_or = A @ x + s * (M @ x)
+        y = to_host(ctx.apply(kap, -1, s, to_dev(x), to_dev(np.zeros(3 * n, complex))))
+        assert rel(y, y_or) <= TOL
+        for b in range(4):
+            xb = Bk.gather(x, dims, b)
+            Ab = Bk.block_operator(A, dims, b)
+            Mb = Bk.block_operator(M, dims, b)
+            yb_or = Ab @ xb + s * (Mb @ xb)
+            yb = to_host(ctx.apply(kap, b, s, to_dev(xb), to_dev(np.zeros(xb.size, complex))))
+            assert rel(yb, yb_or) <= TOL, (kap, b)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 3), (1, 2, 3), (5, 4, 2)])
+def test_apply_odd_full_space(dims):
+    log(f"apply odd dims={dims}")
+    C21, rho = random_spd_field(dims, seed=5)
+    n = int(np.prod(dims))
+    ctx = make_ctx(dims, C21, rho)
+    x = complex_gaussian(3 * n, seed=12345)
+    y_or = P.apply_A(x, dims, KAPPA, C21, rho, s=1.3)
+    y = to_host(ctx.apply(KAPPA, -1, 1.3, to_dev(x), to_dev(np.zeros(3 * n, complex))))
+    assert rel(y, y_or) <= TOL
+    ctx.close()
+
+
+def test_apply_host_pointers():
+    dims = (4, 4, 4)
+    C21, rho = random_spd_field(dims, seed=9)
+    ctx = make_ctx(dims, C21, rho, device_material=False)
+    x = complex_gaussian(192, seed=1)
+    y = np.zeros(192, complex)
+    ctx.apply(KAPPA, -1, 0.0, x, y)
+    assert rel(y, P.apply_A(x, dims, KAPPA, C21, rho)) <= TOL
+    ctx.close()
+
+
+def test_gather_scatter_match_oracle():
+    dims = (6, 4, 8)
+    C21, rho = random_spd_field(dims, seed=2)
+    ctx = make_ctx(dims, C21, rho)
+    x = complex_gaussian(3 * 192, seed=4)
+    full = np.zeros_like(x)
+    for b in range(4):
+        xb = to_host(ctx.gather(b, to_dev(x), to_dev(np.zeros(144, complex))))
+        assert np.array_equal(xb, Bk.gather(x, dims, b))
+        full = to_host(ctx.scatter(b, to_dev(xb), to_dev(full)))
+    assert np.array_equal(full, x)
+    ctx.close()
+
+
+def test_apply_n64_full_sweep():
+    dims = (64, 64, 64)
+    log("apply n=64 two-phase, full sweep")
+    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+    ctx = make_ctx(dims, C21, rho)
+    n = 64 ** 3
+    x = complex_gaussian(3 * n, seed=12345)
+    delta = D.default_shift(C21)
+    y_or = P.apply_A(x, dims, KAPPA, C21, rho, s=delta)
+    y = to_host(ctx.apply(KAPPA, -1, delta, to_dev(x), to_dev(np.zeros(3 * n, complex))))
+    assert rel(y, y_or) <= TOL
+    for b in (0, 3):
+        xb = Bk.gather(x, dims, b)
+        yb = to_host(ctx.apply(KAPPA, b, delta, to_dev(xb), to_dev(np.zeros_like(xb))))
+        assert rel(yb, Bk.gather(y_or, dims, b)) <= TOL
+    ctx.close()
+
+
+def test_apply_n128_sampled():
+    """Benchmark size: sampled outputs, full space and every block."""
+    dims = (128, 128, 128)
+    log("apply n=128 two-phase, sampled")
+    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+    ctx = make_ctx(dims, C21, rho)
+    n = 128 ** 3
+    x = complex_gaussian(3 * n, seed=12345)
+    delta = D.default_shift(C21)
+    rng = np.random.default_rng(7)
+    pts = [tuple(int(v) for v in rng.integers(0, 128, 3)) for _ in range(40)]
+    pts += [(0, 0, 0), (127, 127, 127), (0, 127, 64), (127, 0, 1), (64, 64, 64)]
+    y_pts = P.apply_A_at(pts, x, dims, KAPPA, C21, rho, s=delta)
+    y = to_host(ctx.apply(KAPPA, -1, delta, to_dev(x), to_dev(np.zeros(3 * n, complex))))
+    Y = y.reshape(3, n)
+    idx = [p[0] + 128 * (p[1] + 128 * p[2]) for p in pts]
+    assert rel(Y[:, idx].T, y_pts) <= TOL
+    cls = Bk.node_class(dims)
+    for b in range(4):
+        xb = Bk.gather(x, dims, b)
+        yb = to_host(ctx.apply(KAPPA, b, delta, to_dev(xb), to_dev(np.zeros_like(xb))))
+        nodes = Bk.block_nodes(dims, b)
+        pos = {int(v): t for t, v in enumerate(nodes)}
+        sel = [t for t, p in enumerate(pts) if cls[idx[t]] == b]
+        Yb = yb.reshape(3, -1)
+        got = np.array([Yb[:, pos[idx[t]]] for t in sel])
+        assert rel(got, y_pts[sel]) <= TOL, b
+    ctx.close()

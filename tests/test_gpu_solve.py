@@ -1,0 +1,69 @@
+"""Inner PCG (pbr_solve) vs the direct solution of (A + delta M) x = b."""
+
+import numpy as np
+import pytest
+
+from oracle import blocks as Bk, discretization as D, pointwise as P, solve as S
+from synth import complex_gaussian, random_spd_field, two_phase_cell
+
+from gpu_util import log, make_ctx, rel, to_dev, to_host
+from paper_2606_03599_amd import pbr
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = (0.15, 0.05, 0.10)
+
+
+@pytest.mark.parametrize("kappa", [KAPPA, (0.0, 0.0, 0.0)])
+@pytest.mark.parametrize("precond", [1, 0])
+def test_pcg_matches_direct_n8(kappa, precond):
+    dims = (8, 8, 8)
+    log(f"pcg n=8 kappa={kappa} precond={precond}")
+    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+    ctx = make_ctx(dims, C21, rho)
+    delta = D.default_shift(C21)
+    o = pbr.pbr_opts_default()
+    o.precond = precond
+    o.maxit_inner = 2000
+    b = complex_gaussian(1536, seed=3)
+    x_or = S.shifted_solve(dims, kappa, C21, rho, delta, b)
+    x, st = ctx.solve(kappa, -1, delta, to_dev(b), to_dev(np.zeros_like(b)), o)
+    assert st.converged == 1
+    # relative residual 1e-12 => solution error bounded by cond; check 1e-10
+    assert rel(to_host(x), x_or) <= 1e-10
+    for blk in range(4):
+        bb = Bk.gather(b, dims, blk)
+        xb_or = S.shifted_solve(dims, kappa, C21, rho, delta, bb, block=blk)
+        xb, st = ctx.solve(kappa, blk, delta, to_dev(bb), to_dev(np.zeros_like(bb)), o)
+        assert rel(to_host(xb), xb_or) <= 1e-10
+    ctx.close()
+
+
+def test_pcg_residual_n64_block():
+    dims = (64, 64, 64)
+    log("pcg n=64 block residual")
+    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+    ctx = make_ctx(dims, C21, rho)
+    delta = D.default_shift(C21)
+    b = complex_gaussian(3 * 64 ** 3, seed=5)
+    bb = Bk.gather(b, dims, 2)
+    xb, st = ctx.solve(KAPPA, 2, delta, to_dev(bb), to_dev(np.zeros_like(bb)))
+    x = Bk.scatter(to_host(xb), dims, 2)
+    r = P.apply_A(x, dims, KAPPA, C21, rho, s=delta)
+    rb = Bk.gather(r, dims, 2)
+    assert rel(rb, bb) <= 1e-11
+    log(f"  pcg iterations {st.pcg_iters_total}")
+    ctx.close()
+
+
+def test_pcg_maxit_reports_noconv():
+    dims = (8, 8, 8)
+    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+    ctx = make_ctx(dims, C21, rho)
+    o = pbr.pbr_opts_default()
+    o.maxit_inner = 1
+    b = complex_gaussian(1536, seed=3)
+    with pytest.raises(pbr.PbrError) as e:
+        ctx.solve(KAPPA, -1, 2.0, to_dev(b), to_dev(np.zeros_like(b)), o)
+    assert e.value.status == pbr.PBR_ENOCONV
+    ctx.close()
