@@ -1,0 +1,240 @@
+"""Benchmark: Bloch band path of the parity-blocked solver on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 128] [--nk 16] [--nev 20]
+
+Workload: two-phase unit cube, n^3 grid (default n = 128), cubic matrix
+(C11=1, C12=0.4, C44=0.3, rho=1) with a centred sphere r = 0.35 holding a seeded
+SPD stiffness (rho = 4); 16 points on the Gamma-X-M-Gamma-R path; the 20 lowest
+eigenpairs per point; shift delta = 0.30 C_max; tolerances 1e-12.
+
+One step = the whole hot path over the path: at every k, four parity-block
+shift-invert Krylov solves (inner PCG with the FFT-diagonal preconditioner, the
+fused stencil matvec, Gamma projection) merged with certification.  K steps are
+timed with a device synchronisation on both sides.  The full-space path (one
+solve of 3n unknowns per k) is run once afterwards for the comparison.
+
+Also measured live: the fused block matvec (A + delta M) x at n (4 blocks in
+rotation, HIP events on the context stream), reported against the MI355X HBM
+peak as the roofline of the dominant kernel, and the oracle (CPU) cost of the
+same path estimated from a bounded sample (one oracle matvec + preconditioner
+application at the same n, scaled by the GPU run's PCG iteration count).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = 48 + 168 + 8 + 48   # x, C (21 doubles), rho, y
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1)
+    p.add_argument("--warmup", type=int, default=0)
+    p.add_argument("--n", type=int, default=128)
+    p.add_argument("--nk", type=int, default=16)
+    p.add_argument("--nev", type=int, default=20)
+    p.add_argument("--no-full", action="store_true", help="skip the full-space comparison")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
+    p.add_argument("--matvec-only", action="store_true",
+                   help="only the matvec timing (for hardware-counter runs)")
+    p.add_argument("--mv-iters", type=int, default=100)
+    return p.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def matvec_timing(torch, ctx, n, kappa, delta, iters, blocks=(0, 1, 2, 3)):
+    """Average duration (s) of one (A + delta M) x launch per layout."""
+    from synth import complex_gaussian
+    out = {}
+    for blk in blocks:
+        N = n ** 3 if blk < 0 else n ** 3 // 4
+        x = torch.from_numpy(complex_gaussian(3 * N, seed=12345)).cuda()
+        y = torch.zeros_like(x)
+        for _ in range(10):
+            ctx.apply(kappa, blk, delta, x, y)
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(iters):
+            ctx.apply(kappa, blk, delta, x, y)
+        e.record()
+        torch.cuda.synchronize()
+        out[blk] = s.elapsed_time(e) / 1e3 / iters
+        del x, y
+    return out
+
+
+def copy_peak(torch, nbytes=2 << 30, iters=20):
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(iters):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / 1e3 / iters
+    del a, b
+    return 2 * nbytes / t / 1e9
+
+
+def cpu_sample(n, kappa, C21, rho, delta):
+    """Oracle (as written) cost of one PCG iteration's operator work at this n:
+    one matvec (index formula) and one preconditioner application (numpy.fft),
+    both in the full space, which is how the oracle evaluates a block too."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import fourier as F, pointwise as P
+    from synth import complex_gaussian
+    x = complex_gaussian(3 * n ** 3, seed=12345)
+    Cref, rref = F.reference_material(C21, rho)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        y = P.apply_A(x, (n, n, n), kappa, C21, rho, s=delta)
+        t1 = time.perf_counter()
+        z = F.precond_fft(y, (n, n, n), kappa, -1, Cref, rref, delta)
+        t2 = time.perf_counter()
+    assert np.isfinite(z).all()
+    return t1 - t0, t2 - t1
+
+
+def traffic_record(kernel_src, name):
+    """Hardware-counter traffic of the matvec kernel, if it was measured on the
+    current source (profiles/<name>.json records the source hash)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(kernel_src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != h:
+        return None
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU: collectives and sharding are "
+                                   "not part of it, so --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2606_03599_amd import pbr
+    from synth import sc_path, two_phase_cell
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    n = args.n
+    dims = (n, n, n)
+    log(f"workload: two-phase cell n={n}, nk={args.nk}, nev={args.nev}")
+    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+    ctx = pbr.Context(dims)
+    ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
+    delta = ctx.default_shift()
+    kappas, _ = sc_path(args.nk)
+    kap_mv = (0.15, 0.05, 0.10)
+
+    # ---- matvec roofline (dominant kernel), live HIP-event timing ----
+    mv = matvec_timing(torch, ctx, n, kap_mv, delta, args.mv_iters)
+    mv_full = matvec_timing(torch, ctx, n, kap_mv, delta, max(10, args.mv_iters // 4), blocks=(-1,))
+    t_blk = float(np.mean([mv[b] for b in range(4)]))
+    nb = n ** 3 // 4
+    blk_bytes = BYTES_PER_NODE * nb
+    blk_gbs = blk_bytes / t_blk / 1e9
+    full_gbs = BYTES_PER_NODE * n ** 3 / mv_full[-1] / 1e9
+    cpeak = copy_peak(torch)
+    log(f"block matvec {t_blk*1e6:.1f} us = {blk_gbs:.0f} GB/s; full {mv_full[-1]*1e6:.1f} us = "
+        f"{full_gbs:.0f} GB/s; copy peak {cpeak:.0f} GB/s")
+    rec = traffic_record(os.path.join(ROOT, "paper_2606_03599_amd", "csrc", "stencil.hip"),
+                         f"matvec_block_n{n}_traffic")
+    roof = {"bound": "hbm", "achieved": round(blk_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(blk_gbs / HBM_PEAK_GBS, 4),
+            "traffic": (None if rec is None else rec["hbm_bytes_per_launch"]),
+            "kernel": "fused block stencil (A + delta M) x", "algorithmic_bytes": blk_bytes,
+            "avg_launch_us": round(t_blk * 1e6, 2)}
+    if args.matvec_only:
+        print(json.dumps({"roofline": roof, "full_matvec_GBps": round(full_gbs, 1),
+                          "copy_peak_GBps": round(cpeak, 1)}))
+        ctx.close()
+        return
+
+    # ---- the timed steps: blocked band path ----
+    for w in range(args.warmup):
+        log(f"warmup {w}")
+        ctx.band_path(kappas, args.nev, blocked=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev, st = ctx.band_path(kappas, args.nev, blocked=True)
+        log(f"step {k}: {st.seconds:.2f} s, op_applies {st.op_applies}, pcg avg {st.pcg_avg:.1f}")
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / max(1, args.steps)
+    out = {
+        "metric": "block matvec GB/s (% HBM peak) + Bloch-path s at n=128, vs full-space, 1 GPU",
+        "value": round(t_step, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"two-phase unit cube n={n}^3, {args.nk}-point Gamma-X-M-Gamma-R "
+                               f"path, {args.nev} lowest eigenpairs per k, 4 parity blocks with "
+                               "certified merge, shift-invert Lanczos + FFT-preconditioned PCG, "
+                               "complex128", "n": n, "nk": args.nk, "nev": args.nev,
+                   "tol": 1e-12, "tol_inner": 1e-12, "radius": 0.35, "seed": 0},
+        "block_matvec_GBps": round(blk_gbs, 1),
+        "block_matvec_frac_hbm": round(blk_gbs / HBM_PEAK_GBS, 4),
+        "full_matvec_GBps": round(full_gbs, 1),
+        "copy_peak_GBps": round(cpeak, 1),
+        "pcg_avg": round(st.pcg_avg, 2), "pcg_max": st.pcg_iters_max,
+        "op_applies": st.op_applies, "outer_restarts": st.outer_iters,
+        "max_rel_resid": st.max_rel_resid,
+        "roofline": roof,
+    }
+    # ---- full-space comparison (same GPU, same accuracy) ----
+    if not args.no_full:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evf, stf = ctx.band_path(kappas, args.nev, blocked=False)
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - t0
+        diff = float(np.max(np.abs(ev - evf) / np.abs(evf)))
+        log(f"full-space path {t_full:.2f} s (blocked {t_step:.2f} s), max rel diff {diff:.2e}")
+        out.update({"full_space_path_s": round(t_full, 3),
+                    "blocked_speedup_vs_full": round(t_full / t_step, 3),
+                    "max_rel_diff_blocked_vs_full": diff,
+                    "full_pcg_avg": round(stf.pcg_avg, 2), "full_op_applies": stf.op_applies})
+    ctx.close()
+    # ---- CPU oracle baseline (bounded sample, scaled to the path) ----
+    if not args.no_cpu:
+        t_mv, t_pc = cpu_sample(n, kap_mv, C21, rho, delta)
+        iters = st.pcg_iters_total
+        est = iters * (t_mv + t_pc)
+        out["cpu_baseline"] = {
+            "value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"one oracle matvec ({t_mv:.2f} s) + one oracle FFT preconditioner "
+                       f"({t_pc:.2f} s) at n={n}, single-threaded; scaled by the {iters} PCG "
+                       "iterations of the GPU blocked path (the oracle applies a block as the "
+                       "full-space operator on a zero-extended vector)")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

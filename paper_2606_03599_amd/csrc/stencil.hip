@@ -10,47 +10,141 @@
 //   tau = C(z) eps,   S = stress tensor of tau (S11=t1, S22=t2, S33=t3,
 //                                               S23=t4, S13=t5, S12=t6)
 //   y_a(x) = sum_d sum_m cf[m][d] S_{m,a}(x + d) + s rho(x) v_a(x)   (rows of B)
+//
+// Kernel organisation (one fused pass, HBM-bound):
+//  * a work-group owns a TI x TJ tile of the (i, j) plane of the layout box and
+//    streams through a chunk of planes k in [k0, k1);
+//  * the velocity is staged in LDS once per plane for the tile and the ring its
+//    backward neighbours reach, in a rolling window of three planes.  Staging
+//    multiplies every value by the Bloch phase of its (possibly out-of-box)
+//    position, i.e. it stores the extended field v(x + n_l e_l) = e^{i phi_l} v(x)
+//    of Eq. 3.2, so no later step needs wrap or phase logic;
+//  * for each plane s, tau is formed once per node of the tile plus the ring its
+//    forward neighbours reach (i+1 column, j-1 / j+TJ rows) -- one lane per
+//    position: the tile's lanes plus one extra wave for the ring -- from the
+//    staged velocity and the stiffness (prefetched one plane ahead in registers),
+//    and staged in LDS;
+//  * every output node adds the contributions of plane s to three rolling
+//    accumulators (planes s-1, s, s+1: a forward step changes k by -1, 0 or +1)
+//    and writes plane s-1, now complete, together with s rho x;
+//  * ring positions no output of the tile reaches (parity-dependent in a block
+//    layout, where a step changes y2 by 0 or w2(i)) are skipped;
+//  * tiles are numbered so that consecutive tiles go to one XCD, keeping the
+//    ring re-reads of C and x in that XCD's L2;
+//  * all global accesses are buffer loads/stores with 32-bit offsets (one
+//    descriptor per array, scalar plane offsets).
 #include "context.hpp"
 
 namespace {
 
 struct ApplyArgs {
   Geo g;
-  long N;
+  int N;              // nodes of the layout (all offsets below fit in 32 bits)
   double s;
-  const cplx* __restrict__ x;
-  cplx* __restrict__ y;
-  const double* __restrict__ C;
-  const double* __restrict__ rho;
+  int tiles_i, tiles_j, chunk;
+  const cplx* x;
+  cplx* y;
+  const double* C;
+  const double* rho;
 };
 
-__device__ inline void coords(const Geo& g, long t, int& i, int& j, int& k) {
-  i = (int)(t % g.L1);
-  long r = t / g.L1;
-  j = (int)(r % g.L2);
-  k = (int)(r / g.L2);
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Buffer resources: one 128-bit descriptor per array, so every access is a
+// 32-bit per-lane byte offset plus a wave-uniform (scalar) offset.
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ inline double ldd(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ inline cplx ldc(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(cplx, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ inline void stc(__amdgpu_buffer_rsrc_t r, cplx v, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
 }
 
-// Voigt stress at node z (layout index tz with coordinates i,j,k).
-__device__ void stress_at(const ApplyArgs& A, long tz, int i, int j, int k, cplx tau[6]) {
-  const Geo& g = A.g;
-  const long N = A.N;
-  cplx G[3][3];
-  for (int m = 0; m < 3; ++m)
-    for (int a = 0; a < 3; ++a) G[m][a] = mk(0, 0);
-  // d = 0: the node itself
-  for (int a = 0; a < 3; ++a) {
-    const cplx v = A.x[a * N + tz];
-    for (int m = 0; m < 3; ++m) G[m][a] = cfma(g.cf[m][0], v, G[m][a]);
+// Byte offset outside every buffer: loads through it return 0 without memory
+// traffic, so lanes with nothing to load run the same straight-line code.
+constexpr int OOB = 0x7ffffff0;
+
+// e^{i q phi} from e^{i phi} for any integer q (|q| > 1 only on tiny grids).
+__device__ inline cplx phase_pow(cplx ph, int q) {
+  cplx r = mk(1.0, 0.0);
+  const cplx b = q >= 0 ? ph : cconj(ph);
+  for (int t = q >= 0 ? q : -q; t > 0; --t) r = cmul(r, b);
+  return r;
+}
+
+// Wrap a virtual coordinate into [0, L) and return the number of periods crossed.
+__device__ inline int wrapq(int v, int L, int& q) {
+  q = (v >= 0) ? v / L : -((L - 1 - v) / L);
+  return v - q * L;
+}
+
+// Offsets (dj, dk) of the backward step d (1..4) from a node with first coordinate i.
+__device__ inline void bwd_offsets(const Geo& g, int i, int d, int& dj, int& dk) {
+  const int s2 = step_s2(d), s3 = step_s3(d);
+  if (!g.blocked) {
+    dj = -s2;
+    dk = -s3;
+  } else {
+    const int w2 = 2 * ((g.a + i) & 1) - 1;
+    const int w3 = 2 * ((g.a + g.c + i) & 1) - 1;
+    dj = (w2 - s2) / 2;
+    dk = (w3 - s3) / 2;
   }
+}
+
+// Forward offsets (e2, e3) of step d (1..4) from a node with first coordinate i.
+__device__ inline void fwd_offsets(const Geo& g, int i, int d, int& e2, int& e3) {
+  const int s2 = step_s2(d), s3 = step_s3(d);
+  if (!g.blocked) {
+    e2 = s2;
+    e3 = s3;
+  } else {
+    const int w2 = 2 * ((g.a + i) & 1) - 1;
+    const int w3 = 2 * ((g.a + g.c + i) & 1) - 1;
+    e2 = (s2 + w2) / 2;
+    e3 = (s3 + w3) / 2;
+  }
+}
+
+// Is tau position (ii, jj) of the tile, at virtual plane s, reached by an
+// output node of the tile with plane in [k0, k1)?  (self term or a forward step)
+__device__ inline bool position_needed(const Geo& g, int TI, int TJ, int i0, int j0, int iend,
+                                       int jend, int k0, int k1, int ii, int jj, int s) {
+  const int vi = i0 + ii, vj = j0 - 1 + jj;
+  if (ii < TI && jj >= 1 && jj <= TJ && vi < iend && vj < jend && s >= k0 && s < k1) return true;
+  const int src_i = vi - 1;
+  if (src_i < i0 || src_i >= iend) return false;
+  bool need = false;
+#pragma unroll
   for (int d = 1; d <= 4; ++d) {
-    cplx fac;
-    const long tb = neighbor(g, i, j, k, d, -1, fac);
-    for (int a = 0; a < 3; ++a) {
-      const cplx v = cmul(fac, A.x[a * N + tb]);
-      for (int m = 0; m < 3; ++m) G[m][a] = cfma(g.cf[m][d], v, G[m][a]);
-    }
+    int e2, e3;
+    fwd_offsets(g, src_i, d, e2, e3);
+    const int sj = vj - e2, st = s - e3;
+    need = need || (sj >= j0 && sj < jend && st >= k0 && st < k1);
   }
+  return need;
+}
+
+// Voigt stress from the velocity at the node (v0) and at its four backward
+// neighbours (vb), and the node's stiffness (upper triangle, row by row).
+__device__ inline void stress(const Geo& g, const cplx v0[3], const cplx vb[4][3],
+                              const double Cz[21], cplx tau[6]) {
+  cplx G[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      cplx acc = cscale(g.cf[m][0], v0[a]);
+#pragma unroll
+      for (int d = 1; d <= 4; ++d) acc = cfma(g.cf[m][d], vb[d - 1][a], acc);
+      G[m][a] = acc;
+    }
   cplx eps[6];
   eps[0] = G[0][0];
   eps[1] = G[1][1];
@@ -58,68 +152,309 @@ __device__ void stress_at(const ApplyArgs& A, long tz, int i, int j, int k, cplx
   eps[3] = cadd(G[2][1], G[1][2]);
   eps[4] = cadd(G[2][0], G[0][2]);
   eps[5] = cadd(G[1][0], G[0][1]);
-  double Cz[21];
-  for (int q = 0; q < 21; ++q) Cz[q] = A.C[(long)q * N + tz];
-  // symmetric 6x6 from its upper triangle, row by row
-  int q = 0;
-  double Cm[6][6];
-  for (int r = 0; r < 6; ++r)
-    for (int cc = r; cc < 6; ++cc) {
-      Cm[r][cc] = Cz[q];
-      Cm[cc][r] = Cz[q];
-      ++q;
-    }
+#define CIDX(r, c) ((r) <= (c) ? ((r) * 6 - ((r) * ((r)-1)) / 2 + ((c) - (r))) \
+                               : ((c) * 6 - ((c) * ((c)-1)) / 2 + ((r) - (c))))
+#pragma unroll
   for (int r = 0; r < 6; ++r) {
     cplx acc = mk(0, 0);
-    for (int cc = 0; cc < 6; ++cc) acc = cfma(Cm[r][cc], eps[cc], acc);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc = cfma(Cz[CIDX(r, c)], eps[c], acc);
     tau[r] = acc;
+  }
+#undef CIDX
+}
+
+// y_a contribution sum_m cf[m][d] S_{m,a} of the staged stress at LDS position p.
+template <int NP>
+__device__ inline void contrib(const Geo& g, const cplx* lds, int p, int d, cplx out[3]) {
+  const cplx t0 = lds[0 * NP + p], t1 = lds[1 * NP + p], t2 = lds[2 * NP + p];
+  const cplx t3 = lds[3 * NP + p], t4 = lds[4 * NP + p], t5 = lds[5 * NP + p];
+  // S rows: (t0 t5 t4), (t5 t1 t3), (t4 t3 t2)
+  const double c0 = g.cf[0][d], c1 = g.cf[1][d], c2 = g.cf[2][d];
+  out[0] = cfma(c2, t4, cfma(c1, t5, cscale(c0, t0)));
+  out[1] = cfma(c2, t3, cfma(c1, t1, cscale(c0, t5)));
+  out[2] = cfma(c2, t2, cfma(c1, t3, cscale(c0, t4)));
+}
+
+__device__ inline int wslot(int v) { return ((v % 3) + 3) % 3; }
+
+// Work-group layout: TI*TJ "own" lanes (one output column each) followed by one
+// wave of ring lanes (the i+1 column and the j-1 / j+TJ rows of the tile).
+template <int TI, int TJ>
+__global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A) {
+  constexpr int PI = TI + 1, PJ = TJ + 2, NP = PI * PJ;  // tau region
+  constexpr int XI = TI + 2, XJ = TJ + 4, NX = XI * XJ;  // velocity region
+  constexpr int NOWN = TI * TJ;
+  constexpr int NT = NOWN + 64;
+  constexpr int NH = PJ + 2 * TI;
+  constexpr int XPASS = (NX + NT - 1) / NT;
+  static_assert(NH <= 64, "tau ring must fit in one wave");
+  __shared__ cplx tau_s[6 * NP];
+  __shared__ cplx x_s[3][3 * NX];
+  const Geo& g = A.g;
+  const int L1 = g.L1, L2 = g.L2, L3 = g.L3;
+  const int N = A.N;
+  const __amdgpu_buffer_rsrc_t rx = rsrc(A.x, (unsigned)N * 48u);
+  const __amdgpu_buffer_rsrc_t ry = rsrc(A.y, (unsigned)N * 48u);
+  const __amdgpu_buffer_rsrc_t rc = rsrc(A.C, (unsigned)N * 168u);
+  const __amdgpu_buffer_rsrc_t rr = rsrc(A.rho, (unsigned)N * 8u);
+  const int cs = N * 16, ds = N * 8;
+
+  // XCD-aware numbering: work-groups are dealt round-robin over 8 XCDs, so
+  // give each XCD a contiguous range of (tile, chunk) indices.
+  const int W = gridDim.x;
+  const int w = blockIdx.x;
+  const int per = W / 8, rem = W % 8;
+  const int xcd = w % 8, slot = w / 8;
+  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+  const int ntile = A.tiles_i * A.tiles_j;
+  const int tile = logical % ntile;
+  const int chunk = logical / ntile;
+  const int i0 = (tile % A.tiles_i) * TI;
+  const int j0 = (tile / A.tiles_i) * TJ;
+  const int k0 = chunk * A.chunk;
+  const int k1 = min(k0 + A.chunk, L3);
+  const int iend = min(i0 + TI, L1), jend = min(j0 + TJ, L2);
+  const int tid = threadIdx.x;
+
+  // ---- velocity staging positions of this lane (XPASS per plane) ----
+  int xoff[XPASS];     // byte offset of the actual node in one component plane
+  cplx xph[XPASS];     // in-plane Bloch phase of the virtual position
+#pragma unroll
+  for (int r = 0; r < XPASS; ++r) {
+    const int p = tid + r * NT;
+    const int xc = p % XI, xr = p / XI;
+    int qi, qj;
+    const int ai = wrapq(i0 - 1 + xc, L1, qi);
+    const int aj = wrapq(j0 - 2 + xr, L2, qj);
+    xoff[r] = (p < NX) ? (ai + L1 * aj) * 16 : OOB;
+    xph[r] = cmul(phase_pow(g.ph[0], qi), phase_pow(g.ph[1], qj));
+  }
+  auto stage_load = [&](int v, cplx out[XPASS][3]) {
+    int qk;
+    const int kk = wrapq(v, L3, qk);
+    const int kb = kk * L1 * L2 * 16;
+#pragma unroll
+    for (int r = 0; r < XPASS; ++r)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        out[r][a] = ldc(rx, xoff[r] == OOB ? OOB : xoff[r] + kb, a * cs);
+  };
+  auto stage_store = [&](int v, cplx in[XPASS][3]) {
+    int qk;
+    (void)wrapq(v, L3, qk);
+    const cplx phk = phase_pow(g.ph[2], qk);
+    cplx* dst = x_s[wslot(v)];
+#pragma unroll
+    for (int r = 0; r < XPASS; ++r) {
+      const int p = tid + r * NT;
+      if (p < NX) {
+        const cplx ph = cmul(phk, xph[r]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dst[a * NX + p] = cmul(ph, in[r][a]);
+      }
+    }
+  };
+
+  // ---- this lane's tau position ----
+  const bool own = tid < NOWN;
+  const int h = tid - NOWN;
+  int ii, jj;
+  if (own) {
+    ii = tid % TI;
+    jj = tid / TI + 1;
+  } else {
+    ii = (h < PJ) ? TI : (h < PJ + TI ? h - PJ : h - PJ - TI);
+    jj = (h < PJ) ? h : (h < PJ + TI ? 0 : PJ - 1);
+  }
+  const bool active = own || h < NH;
+  const int vi = i0 + ii, vj = j0 - 1 + jj;
+  int qi0, qj0;
+  const int ai = wrapq(vi, L1, qi0);
+  const int aj = wrapq(vj, L2, qj0);
+  const int pos = jj * PI + ii;
+  // LDS velocity indices of the node and its backward neighbours, and the
+  // window plane offset of each neighbour
+  const int xself = (jj + 1) * XI + ii + 1;
+  int xnb[4], dkn[4];
+#pragma unroll
+  for (int d = 1; d <= 4; ++d) {
+    int dj, dk;
+    bwd_offsets(g, ai, d, dj, dk);
+    xnb[d - 1] = (jj + dj + 1) * XI + ii;
+    dkn[d - 1] = dk;
+  }
+  const bool inbox_pos = own && vi < iend && vj < jend;
+  auto needed_at = [&](int s) -> bool {
+    if (!active) return false;
+    if (inbox_pos && s >= k0 && s < k1) return true;
+    return position_needed(g, TI, TJ, i0, j0, iend, jend, k0, k1, ii, jj, s);
+  };
+  auto load_C = [&](int s, bool need, double Cz[21], double& rz) {
+    int qk;
+    const int kk = wrapq(s, L3, qk);
+    const int o8 = need ? (ai + L1 * (aj + L2 * kk)) * 8 : OOB;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Cz[q] = ldd(rc, o8, q * ds);
+    rz = ldd(rr, o8, 0);
+  };
+
+  // ---- output (own lanes) ----
+  const int io = vi, jo = vj;
+  const bool out_ok = own && io < L1 && jo < L2;
+  const int w2 = g.blocked ? 2 * ((g.a + io) & 1) - 1 : 0;
+  const int w3p = g.blocked ? (((g.a + g.c + io) & 1) ? 1 : 0) : 0;
+  const int eA = g.blocked ? (w2 > 0 ? 1 : 0) : 1;
+  const int eB = g.blocked ? (w2 > 0 ? 0 : -1) : -1;
+  const int pA = (jj + eA) * PI + ii + 1;
+  const int pB = (jj + eB) * PI + ii + 1;
+
+  cplx A0[3], A1[3], A2[3];  // outputs of planes s-1, s, s+1
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A0[a] = A1[a] = A2[a] = mk(0, 0);
+  cplx xprev[3];
+  double rprev = 0.0;
+
+  // ---- prologue: velocity planes k0-2 .. k0, stiffness of tau plane k0-1 ----
+  {
+    cplx buf[XPASS][3];
+    for (int v = k0 - 2; v <= k0; ++v) {
+      stage_load(v, buf);
+      stage_store(v, buf);
+    }
+  }
+  bool need_cur = needed_at(k0 - 1);
+  double Ccur[21], rcur;
+  load_C(k0 - 1, need_cur, Ccur, rcur);
+  __syncthreads();
+
+  for (int s = k0 - 1; s <= k1; ++s) {
+    // issue the loads of the next stiffness plane and of velocity plane s+2
+    const bool need_nxt = (s + 1 <= k1) && needed_at(s + 1);
+    double Cnxt[21], rnxt;
+    load_C(s + 1, need_nxt, Cnxt, rnxt);
+    cplx xnext[XPASS][3];
+    const bool more_x = s + 2 <= k1 + 1;
+    if (more_x) stage_load(s + 2, xnext);
+    // ---- tau of plane s from the staged velocity ----
+    const cplx* xs0 = x_s[wslot(s)];
+    // the shift term of output plane s-1 needs x(s-1) before its slot is reused
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xprev[a] = x_s[wslot(s - 1)][a * NX + xself];
+    if (need_cur) {
+      cplx v0[3], vb[4][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v0[a] = xs0[a * NX + xself];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const cplx* xsd = x_s[wslot(s + dkn[d])];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vb[d][a] = xsd[a * NX + xnb[d]];
+      }
+      cplx tau[6];
+      stress(g, v0, vb, Ccur, tau);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tau_s[c * NP + pos] = tau[c];
+    }
+    __syncthreads();
+    // ---- consume plane s ----
+    if (out_ok) {
+      cplx c1[3], c3[3], gP[3], gM[3];
+      contrib<NP>(g, tau_s, pA, 1, c1);
+      contrib<NP>(g, tau_s, pB, 3, c3);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gP[a] = cadd(c1[a], c3[a]);
+      contrib<NP>(g, tau_s, pA, 2, c1);
+      contrib<NP>(g, tau_s, pB, 4, c3);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gM[a] = cadd(c1[a], c3[a]);
+      if (s >= k0 && s < k1) {
+        const cplx t0 = tau_s[0 * NP + pos], t5 = tau_s[5 * NP + pos];
+        const cplx t4 = tau_s[4 * NP + pos], t1 = tau_s[1 * NP + pos];
+        const cplx t3 = tau_s[3 * NP + pos], t2 = tau_s[2 * NP + pos];
+        const double a0 = g.cf[0][0], a1 = g.cf[1][0], a2 = g.cf[2][0];
+        A1[0] = cadd(A1[0], cfma(a2, t4, cfma(a1, t5, cscale(a0, t0))));
+        A1[1] = cadd(A1[1], cfma(a2, t3, cfma(a1, t1, cscale(a0, t5))));
+        A1[2] = cadd(A1[2], cfma(a2, t2, cfma(a1, t3, cscale(a0, t4))));
+      }
+      // forward steps with s3 = +1 / -1 reach plane s from output plane s - e3:
+      // natural layout e3 = s3; block layout e3 = 0 or w3.
+      if (!g.blocked) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          A0[a] = cadd(A0[a], gP[a]);
+          A2[a] = cadd(A2[a], gM[a]);
+        }
+      } else if (w3p) {  // w3 = +1: s3=+1 -> e3 = +1, s3=-1 -> e3 = 0
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          A0[a] = cadd(A0[a], gP[a]);
+          A1[a] = cadd(A1[a], gM[a]);
+        }
+      } else {  // w3 = -1: s3=+1 -> e3 = 0, s3=-1 -> e3 = -1
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          A1[a] = cadd(A1[a], gP[a]);
+          A2[a] = cadd(A2[a], gM[a]);
+        }
+      }
+      // ---- plane s-1 is complete: y = B C B^H x + shift rho x ----
+      const int t = s - 1;
+      if (t >= k0 && t < k1) {
+        const int o = io + L1 * (jo + L2 * t);
+        const double sr = A.s * rprev;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) stc(ry, cfma(sr, xprev[a], A0[a]), o * 16, a * cs);
+      }
+    }
+    // velocity plane s+2 replaces plane s-1 in the window
+    if (more_x) stage_store(s + 2, xnext);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      A0[a] = A1[a];
+      A1[a] = A2[a];
+      A2[a] = mk(0, 0);
+    }
+    rprev = rcur;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Ccur[q] = Cnxt[q];
+    rcur = rnxt;
+    need_cur = need_nxt;
+    __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(256) apply_gather_kernel(ApplyArgs A) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= A.N) return;
-  const Geo& g = A.g;
-  int i, j, k;
-  coords(g, t, i, j, k);
-  cplx y[3] = {mk(0, 0), mk(0, 0), mk(0, 0)};
-  for (int d = 0; d <= 4; ++d) {
-    long tz = t;
-    cplx fac = mk(1, 0);
-    int zi = i, zj = j, zk = k;
-    if (d > 0) {
-      tz = neighbor(g, i, j, k, d, +1, fac);
-      coords(g, tz, zi, zj, zk);
-    }
-    cplx tau[6];
-    stress_at(A, tz, zi, zj, zk, tau);
-    // S_{m,a}: row m of the symmetric stress tensor
-    const cplx S[3][3] = {{tau[0], tau[5], tau[4]},
-                          {tau[5], tau[1], tau[3]},
-                          {tau[4], tau[3], tau[2]}};
-    for (int a = 0; a < 3; ++a) {
-      cplx acc = mk(0, 0);
-      for (int m = 0; m < 3; ++m) acc = cfma(g.cf[m][d], S[m][a], acc);
-      y[a] = cmad(fac, acc, y[a]);
-    }
-  }
-  const double sr = A.s * A.rho[t];
-  for (int a = 0; a < 3; ++a) A.y[a * A.N + t] = cfma(sr, A.x[a * A.N + t], y[a]);
-}
+constexpr int TILE_I = 16, TILE_J = 16;
 
 }  // namespace
 
 int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y) {
   DevMaterial& M = c->material(block);
+  if (M.N * 168L >= (1L << 31)) {
+    c->set_error("grid too large for 32-bit buffer offsets of the stencil kernel");
+    return ST_EINVAL;
+  }
   ApplyArgs A;
   A.g = g;
-  A.N = M.N;
+  A.N = (int)M.N;
   A.s = s;
   A.x = x;
   A.y = y;
   A.C = M.C;
   A.rho = M.rho;
-  hipLaunchKernelGGL(apply_gather_kernel, dim3(ceil_div(M.N, 256)), dim3(256), 0, c->stream, A);
+  A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
+  A.tiles_j = (g.L2 + TILE_J - 1) / TILE_J;
+  // chunk length: about one work-group per CU (256 CUs); longer chunks amortise
+  // the two partial planes a chunk stages at its ends
+  const long tiles = (long)A.tiles_i * A.tiles_j;
+  int chunk = (int)std::max<long>(1, (tiles * g.L3) / 256);
+  chunk = std::max(chunk, 4);
+  chunk = std::min(chunk, g.L3);
+  A.chunk = chunk;
+  const int nchunks = (g.L3 + chunk - 1) / chunk;
+  const unsigned grid = (unsigned)(tiles * nchunks);
+  hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
+                     dim3(TILE_I * TILE_J + 64), 0, c->stream, A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
