@@ -3,24 +3,30 @@
 // with the Bloch Fourier basis T (Sec. 5.1, Eqs. 5.1-5.2) in the full space and
 // T_sigma = T F_sigma (Sec. 5.2, Eqs. 5.3-5.5) in a parity block.
 //
-// Full space: coefficient(m) = sum_x e^{-i x.theta_m} r(x), theta_m =
-// ((phi1 + 2 pi p)/n1, ...): a twist by e^{-i x_l phi_l/n_l} followed by a
-// plain 3D DFT.
+// Full space: coefficient(m) = sum_x e^{-i x.theta_m} r(x) with theta_m =
+// ((phi1 + 2 pi p)/n1, ...): a twist e^{-i x_l phi_l/n_l} and a 3D DFT.
 //
-// Block b: the nodes are (i, 2 y2 + o2(i), 2 y3 + o3(i)).  Taking the orbit
-// representatives m = (p, q, r) with q < n2/2, r < n3/2 (one per orbit of
-// Eq. 5.3), the block coefficient is a 3D DFT on the L1 x L2 x L3 = n1 x n2/2 x
-// n3/2 box: along y2 a twist e^{-i y2 phi2/(n2/2)} and a length-n2/2 DFT, then
-// the factor e^{-i o2(i) beta_q} (beta_q = (phi2 + 2 pi q)/n2) -- the half-node
-// offset of the sub-lattice, which folds the orbit as F_sigma does -- likewise
-// along y3, and finally a twisted length-n1 DFT along i.  Because the y2/y3
-// factors depend on i, the y2 and y3 passes run before the i pass (and after it
-// on the way back).  K(m) is the same on every orbit member (Sec. 5.3), so one
-// 3x3 solve per representative suffices.
+// Block b: its nodes form two simple-cubic sub-lattices, p = i mod 2, node
+// (2i'+p, 2y2+o2(p), 2y3+o3(p)) with o2 = (a+p) mod 2, o3 = (a+c+p) mod 2.  For
+// the orbit representatives m = (m1, q, r), q < n2/2, r < n3/2 (one per orbit
+// of Eq. 5.3) the block coefficient splits into the two sub-lattice transforms
+//     V_p(m1', q, r) = sum e^{-i(2i' alpha + 2 y2 beta + 2 y3 gamma)} r_p,
+// plain twisted 3D DFTs of size n1/2 x n2/2 x n3/2, combined pointwise:
+//     c_b = T_0 V_0 + (-1)^b e^{-i alpha} T_1 V_1,   m1 = m1' + b n1/2,
+//     T_p = e^{-i(o2(p) beta_q + o3(p) gamma_r)},
+// which is the folding F_sigma of Eq. 5.4 written in sub-lattice variables.
+// K(m) is the same on every member of an orbit (Sec. 5.3), so the block
+// preconditioner is: sub-lattice DFTs, fold, two 3x3 solves, unfold, inverse.
 //
+// Passes (each reads and writes the 3-component vector once; the first
+// pass reads r, every later pass works in place on z):
+//   1. i axis: length-n1 lines, split into even/odd half lines for a block;
+//   2. j (y2) axis;
+//   3. k (y3) axis forward, fold + 3x3 Cholesky solves + unfold per mode,
+//      k axis inverse -- all in LDS;
+//   4. j axis inverse;   5. i axis inverse, times 1/N.
 // Every 1D transform is a mixed radix-4/2/3 Stockham FFT in LDS on a batch of
-// lines; lines along y2/y3 are batched over consecutive i for coalesced access.
-// All transforms are unnormalised; the final pass multiplies by 1/N.
+// lines; lines along j and k are batched over consecutive i for coalescing.
 #include <cmath>
 #include <vector>
 
@@ -29,247 +35,233 @@
 namespace {
 
 constexpr int FFT_THREADS = 256;
-constexpr int FFT_ELEMS = 2048;  // complex elements per work-group batch (32 KB per buffer)
-
-struct AxisArgs {
-  int L1, L2, L3;
-  int axis;          // 0, 1, 2
-  int L;             // line length
-  long nlines;       // lines per component
-  long N;            // nodes per component
-  int B;             // lines per work-group
-  int nfac;
-  int fac[12];       // radices in order
-  int sign;          // -1 forward, +1 inverse
-  const cplx* __restrict__ roots;  // e^{-2 pi i k/L}
-  const cplx* __restrict__ pre;    // per element factor (or null)
-  int pre_conj;
-  const cplx* __restrict__ post;   // per output element factor (or null)
-  int post_conj;
-  int parity_mode;   // 0: pre/post for every line; 1: post/pre only on lines with odd o(i)
-  int par_off;       // o(i) = (par_off + i) & 1
-  int pre_is_parity; // pre factor is the parity factor (inverse direction)
-  double scale;
-  const cplx* in;
-  cplx* out;
-};
-
-__device__ inline long line_base(const AxisArgs& A, long l, long& estride, int& iline) {
-  if (A.axis == 0) {
-    estride = 1;
-    iline = 0;
-    return l * A.L1;
-  } else if (A.axis == 1) {
-    estride = A.L1;
-    iline = (int)(l % A.L1);
-    return (l % A.L1) + (l / A.L1) * (long)A.L1 * A.L2;
-  }
-  estride = (long)A.L1 * A.L2;
-  iline = (int)(l % A.L1);
-  return l;
-}
+constexpr int FFT_ELEMS = 1024;  // complex elements per LDS buffer of a line batch
 
 __device__ inline cplx cj(cplx a, int c) { return c ? cconj(a) : a; }
 
-template <int R>
-__device__ inline void small_dft(cplx* v, int sign) {
-  if (R == 2) {
+template <int R, int SIGN>
+__device__ inline void small_dft(cplx* v) {
+  if constexpr (R == 2) {
     const cplx a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     const cplx t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
     const cplx t2 = cadd(v[1], v[3]);
     const cplx d = csub(v[1], v[3]);
-    // multiply by w = sign * i
-    const cplx t3 = (sign < 0) ? mk(d.y, -d.x) : mk(-d.y, d.x);
+    const cplx t3 = (SIGN < 0) ? mk(d.y, -d.x) : mk(-d.y, d.x);  // d * (SIGN i)
     v[0] = cadd(t0, t2);
     v[2] = csub(t0, t2);
     v[1] = cadd(t1, t3);
     v[3] = csub(t1, t3);
-  } else if (R == 3) {
+  } else {
+    static_assert(R == 3, "radix");
     const double h = 0.86602540378443864676;  // sqrt(3)/2
     const cplx t = cadd(v[1], v[2]);
     const cplx u = csub(v[1], v[2]);
     const cplx m = mk(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
-    // s * i * h * u
-    const cplx iu = (sign < 0) ? mk(h * u.y, -h * u.x) : mk(-h * u.y, h * u.x);
+    const cplx iu = (SIGN < 0) ? mk(h * u.y, -h * u.x) : mk(-h * u.y, h * u.x);
     v[0] = cadd(v[0], t);
     v[1] = cadd(m, iu);
     v[2] = csub(m, iu);
   }
 }
 
-template <int R>
-__device__ inline void stage(const AxisArgs& A, const cplx* src, cplx* dst, int Ns, int nb) {
-  const int L = A.L;
-  const int LR = L / R;
-  const int tw_step = L / (Ns * R);
+// Radix plan of a length 2^a 3^b, fixed at compile time: radix-4 stages, then
+// one radix-2 stage if needed, then radix-3 stages.
+constexpr int plan_nfac(int L) {
+  int n = 0;
+  while (L % 4 == 0) { ++n; L /= 4; }
+  while (L % 2 == 0) { ++n; L /= 2; }
+  while (L % 3 == 0) { ++n; L /= 3; }
+  return n;
+}
+constexpr int plan_fac(int L, int s) {
+  int n = 0;
+  while (L % 4 == 0) { if (n == s) return 4; ++n; L /= 4; }
+  while (L % 2 == 0) { if (n == s) return 2; ++n; L /= 2; }
+  while (L % 3 == 0) { if (n == s) return 3; ++n; L /= 3; }
+  return 1;
+}
+
+// One Stockham stage on nb lines of length L stored back to back in LDS.
+template <int L, int R, int NS, int SIGN>
+__device__ inline void stage(const cplx* __restrict__ roots, const cplx* src, cplx* dst, int nb) {
+  constexpr int LR = L / R;
+  constexpr int TW = L / (NS * R);
   for (int w = threadIdx.x; w < nb * LR; w += blockDim.x) {
     const int b = w / LR;
     const int j = w - b * LR;
-    const int jm = j % Ns;
+    const int jm = j % NS;
     cplx v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       cplx x = src[b * L + j + r * LR];
-      if (r > 0) {
-        const cplx wv = cj(A.roots[(jm * r * tw_step) % L], A.sign > 0);
-        x = cmul(x, wv);
-      }
+      if (r > 0 && NS > 1) x = cmul(x, cj(roots[(jm * r * TW) % L], SIGN > 0));
       v[r] = x;
     }
-    small_dft<R>(v, A.sign);
-    const int idx = (j / Ns) * Ns * R + jm;
+    small_dft<R, SIGN>(v);
+    const int idx = (j / NS) * NS * R + jm;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[b * L + idx + r * Ns] = v[r];
+    for (int r = 0; r < R; ++r) dst[b * L + idx + r * NS] = v[r];
   }
 }
 
-__global__ void __launch_bounds__(FFT_THREADS) fft_axis_kernel(AxisArgs A) {
-  extern __shared__ cplx lds[];
-  cplx* buf0 = lds;
-  cplx* buf1 = lds + FFT_ELEMS;
+// Stages S.. of a length-L transform of nb lines; the input is in a, the
+// other buffer is b; returns the buffer that holds the result.
+template <int L, int S, int NS, int SIGN>
+__device__ inline cplx* fft_stages(const cplx* __restrict__ roots, cplx* a, cplx* b, int nb) {
+  if constexpr (S >= plan_nfac(L)) {
+    return a;
+  } else {
+    constexpr int R = plan_fac(L, S);
+    stage<L, R, NS, SIGN>(roots, a, b, nb);
+    __syncthreads();
+    return fft_stages<L, S + 1, NS * R, SIGN>(roots, b, a, nb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Passes 1, 2, 4, 5: lines along axis 0 (i) or 1 (j).
+// ---------------------------------------------------------------------------
+struct LineArgs {
+  int L1, L2, L3;
+  long nlines;       // lines per component
+  long N;
+  const cplx* __restrict__ roots;
+  const cplx* __restrict__ twist;  // e^{-i y phi / L}, y in [0, L) of the transform
+  double scale;
+  const cplx* in;
+  cplx* out;
+};
+
+// LT: transform length; AXIS: 0 (memory-contiguous lines of length LM) or 1;
+// SPLIT: axis-0 lines of a block, LM = 2 LT, even and odd elements transformed
+// separately.
+template <int LT, int AXIS, int SPLIT, int SIGN>
+__global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
+  constexpr int LM = SPLIT ? 2 * LT : LT;          // line length in memory
+  constexpr int B = (FFT_ELEMS / LM) > 0 ? FFT_ELEMS / LM : 1;  // lines per work-group
+  __shared__ cplx buf0[B * LM], buf1[B * LM];
   const int comp = blockIdx.y;
-  const long l0 = (long)blockIdx.x * A.B;
-  const int nb = (int)min((long)A.B, A.nlines - l0);
+  const long l0 = (long)blockIdx.x * B;
+  const int nb = (int)min((long)B, A.nlines - l0);
   const cplx* in = A.in + comp * A.N;
   cplx* out = A.out + comp * A.N;
-  const int L = A.L;
-  // load (elements of consecutive lines adjacent in memory for axes 1, 2)
-  for (int w = threadIdx.x; w < nb * L; w += blockDim.x) {
+  const long es = AXIS == 0 ? 1 : A.L1;
+  auto base_of = [&](long l) -> long {
+    if (AXIS == 0) return l * LM;
+    return (l % A.L1) + (l / A.L1) * (long)A.L1 * A.L2;
+  };
+  for (int w = threadIdx.x; w < B * LM; w += blockDim.x) {
     int b, e;
-    if (A.axis == 0) {
-      b = w / L;
-      e = w - b * L;
+    if (AXIS == 0) {
+      b = w / LM;
+      e = w - b * LM;
     } else {
-      e = w / nb;
-      b = w - e * nb;
+      e = w / B;
+      b = w - e * B;
     }
-    long es;
-    int il;
-    const long base = line_base(A, l0 + b, es, il);
-    cplx x = in[base + e * es];
-    if (A.pre) {
-      if (A.pre_is_parity) {
-        if (((A.par_off + il) & 1)) x = cmul(x, cj(A.pre[e], A.pre_conj));
-      } else {
-        x = cmul(x, cj(A.pre[e], A.pre_conj));
-      }
+    if (b < nb) {
+      cplx x = in[base_of(l0 + b) + e * es];
+      const int slot = SPLIT ? 2 * b + (e & 1) : b;
+      const int y = SPLIT ? e >> 1 : e;
+      if (SIGN < 0) x = cmul(x, A.twist[y]);
+      buf0[slot * LT + y] = x;
     }
-    buf0[b * L + e] = x;
   }
   __syncthreads();
-  cplx* src = buf0;
-  cplx* dst = buf1;
-  int Ns = 1;
-  for (int s = 0; s < A.nfac; ++s) {
-    const int R = A.fac[s];
-    if (R == 4)
-      stage<4>(A, src, dst, Ns, nb);
-    else if (R == 2)
-      stage<2>(A, src, dst, Ns, nb);
-    else
-      stage<3>(A, src, dst, Ns, nb);
-    __syncthreads();
-    cplx* t = src;
-    src = dst;
-    dst = t;
-    Ns *= R;
-  }
-  for (int w = threadIdx.x; w < nb * L; w += blockDim.x) {
+  const cplx* res = fft_stages<LT, 0, 1, SIGN>(A.roots, buf0, buf1, SPLIT ? 2 * nb : nb);
+  for (int w = threadIdx.x; w < B * LM; w += blockDim.x) {
     int b, e;
-    if (A.axis == 0) {
-      b = w / L;
-      e = w - b * L;
+    if (AXIS == 0) {
+      b = w / LM;
+      e = w - b * LM;
     } else {
-      e = w / nb;
-      b = w - e * nb;
+      e = w / B;
+      b = w - e * B;
     }
-    long es;
-    int il;
-    const long base = line_base(A, l0 + b, es, il);
-    cplx x = src[b * L + e];
-    if (A.post) {
-      if (A.parity_mode) {
-        if (((A.par_off + il) & 1)) x = cmul(x, cj(A.post[e], A.post_conj));
-      } else {
-        x = cmul(x, cj(A.post[e], A.post_conj));
-      }
+    if (b < nb) {
+      const int slot = SPLIT ? 2 * b + (e & 1) : b;
+      const int y = SPLIT ? e >> 1 : e;
+      cplx x = res[slot * LT + y];
+      if (SIGN > 0) x = cmul(x, cconj(A.twist[y]));
+      out[base_of(l0 + b) + e * es] = cscale(A.scale, x);
     }
-    out[base + e * es] = cscale(A.scale, x);
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pass 3: k axis forward, per-mode solve (with the orbit fold for a block),
+// k axis inverse.
+// ---------------------------------------------------------------------------
 struct SolveArgs {
   int L1, L2, L3;
   long N;
-  double th0[3];     // phi_l / n_l
-  double dth[3];     // 2 pi / n_l
+  int a, c;                        // block class bits
+  const cplx* __restrict__ roots;  // length-L3 roots
+  const cplx* __restrict__ twist;  // e^{-i y phi3 / L3}
+  const cplx* __restrict__ e1;     // e^{i alpha_m} = e^{i (phi1 + 2 pi m)/n1}, m < n1
+  const cplx* __restrict__ e2;     // e^{i beta_q},  q < n2
+  const cplx* __restrict__ e3;     // e^{i gamma_r}, r < n3
   double cf[3][5];
   double Cref[21];
-  double shift_rho;  // shift * rho_ref
+  double shift_rho;
   cplx* data;
 };
 
-__global__ void __launch_bounds__(256) mode_solve_kernel(SolveArgs S) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= S.N) return;
-  const int p = (int)(t % S.L1);
-  const long rr = t / S.L1;
-  const int q = (int)(rr % S.L2);
-  const int r = (int)(rr / S.L2);
-  const double al = S.th0[0] + S.dth[0] * p;
-  const double be = S.th0[1] + S.dth[1] * q;
-  const double ga = S.th0[2] + S.dth[2] * r;
-  // shift symbols e^{i d.theta} of the four diagonal steps
+// K(m)^-1 b for the mode whose one-step phases are Ea = e^{i alpha},
+// Eb = e^{i beta}, Eg = e^{i gamma}: the diagonal shifts have symbols
+// e^{i(alpha +- beta +- gamma)} (Eq. 4.1).
+__device__ inline void mode_solve(const SolveArgs& S, cplx Ea, cplx Eb, cplx Eg, const cplx b[3],
+                                  cplx x[3]) {
+  const cplx ab = cmul(Ea, Eb), abc = cmulc(Eb, Ea);  // e^{i(a+b)}, e^{i(a-b)}
   cplx sd[5];
   sd[0] = mk(1.0, 0.0);
-  for (int d = 1; d <= 4; ++d) {
-    const double ang = al + step_s2(d) * be + step_s3(d) * ga;
-    double sn, cs;
-    sincos(ang, &sn, &cs);
-    sd[d] = mk(cs, sn);
-  }
-  // symbols of D'_m (the -i factors cancel in Bhat C Bhat^H)
+  sd[1] = cmul(ab, Eg);
+  sd[2] = cmulc(Eg, ab);
+  sd[3] = cmul(abc, Eg);
+  sd[4] = cmulc(Eg, abc);
+  // symbols of D'_m (the factors -i cancel in Bhat C Bhat^H)
   cplx e[3];
+#pragma unroll
   for (int m = 0; m < 3; ++m) {
     cplx acc = mk(0, 0);
+#pragma unroll
     for (int d = 0; d <= 4; ++d) acc = cfma(S.cf[m][d], sd[d], acc);
     e[m] = acc;
   }
-  // P = Bhat (3x6), rows as in Eq. 5.11
   const cplx z = mk(0, 0);
   const cplx P[3][6] = {{e[0], z, z, z, e[2], e[1]},
                         {z, e[1], z, e[2], z, e[0]},
                         {z, z, e[2], e[1], e[0], z}};
-  double Cm[6][6];
-  {
-    int qq = 0;
-    for (int a = 0; a < 6; ++a)
-      for (int b = a; b < 6; ++b) {
-        Cm[a][b] = S.Cref[qq];
-        Cm[b][a] = S.Cref[qq];
-        ++qq;
-      }
-  }
-  // W = P C (3x6), K = W P^H (3x3 Hermitian)
   cplx W[3][6];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 6; ++b) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int col = 0; col < 6; ++col) {
       cplx acc = mk(0, 0);
-      for (int k = 0; k < 6; ++k) acc = cfma(Cm[k][b], P[a][k], acc);
-      W[a][b] = acc;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int rr = k <= col ? k : col, cc = k <= col ? col : k;
+        const double cv = S.Cref[rr * 6 - (rr * (rr - 1)) / 2 + (cc - rr)];
+        acc = cfma(cv, P[r][k], acc);
+      }
+      W[r][col] = acc;
     }
   cplx K[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
       cplx acc = mk(0, 0);
-      for (int k = 0; k < 6; ++k) acc = cmad(W[a][k], cconj(P[b][k]), acc);
-      K[a][b] = acc;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc = cmad(W[r][k], cconj(P[col][k]), acc);
+      K[r][col] = acc;
     }
-  for (int a = 0; a < 3; ++a) K[a][a].x += S.shift_rho;
-  // Cholesky K = L L^H
+#pragma unroll
+  for (int r = 0; r < 3; ++r) K[r][r].x += S.shift_rho;
+  // Cholesky K = L L^H and the two triangular solves
   const double l00 = sqrt(K[0][0].x);
   const cplx l10 = cscale(1.0 / l00, K[1][0]);
   const cplx l20 = cscale(1.0 / l00, K[2][0]);
@@ -277,62 +269,133 @@ __global__ void __launch_bounds__(256) mode_solve_kernel(SolveArgs S) {
   const cplx l21 = cscale(1.0 / l11, csub(K[2][1], cmul(l20, cconj(l10))));
   const double l22 =
       sqrt(K[2][2].x - (l20.x * l20.x + l20.y * l20.y) - (l21.x * l21.x + l21.y * l21.y));
-  cplx b0 = S.data[t], b1 = S.data[S.N + t], b2 = S.data[2 * S.N + t];
-  const cplx y0 = cscale(1.0 / l00, b0);
-  const cplx y1 = cscale(1.0 / l11, csub(b1, cmul(l10, y0)));
-  const cplx y2 = cscale(1.0 / l22, csub(csub(b2, cmul(l20, y0)), cmul(l21, y1)));
-  const cplx x2 = cscale(1.0 / l22, y2);
-  const cplx x1 = cscale(1.0 / l11, csub(y1, cmulc(l21, x2)));
-  const cplx x0 = cscale(1.0 / l00, csub(csub(y0, cmulc(l10, x1)), cmulc(l20, x2)));
-  S.data[t] = x0;
-  S.data[S.N + t] = x1;
-  S.data[2 * S.N + t] = x2;
+  const cplx y0 = cscale(1.0 / l00, b[0]);
+  const cplx y1 = cscale(1.0 / l11, csub(b[1], cmul(l10, y0)));
+  const cplx y2 = cscale(1.0 / l22, csub(csub(b[2], cmul(l20, y0)), cmul(l21, y1)));
+  x[2] = cscale(1.0 / l22, y2);
+  x[1] = cscale(1.0 / l11, csub(y1, cmulc(l21, x[2])));
+  x[0] = cscale(1.0 / l00, csub(csub(y0, cmulc(l10, x[1])), cmulc(l20, x[2])));
 }
 
-__global__ void table_kernel(int L, double phi, double nfull, int kind, cplx* out) {
+constexpr int solve_bi(int L3, int blocked) {
+  const int b = FFT_ELEMS / (3 * L3);
+  return blocked ? (b >= 2 ? (b & ~1) : 2) : (b >= 1 ? b : 1);
+}
+
+template <int L3T, int BLK>
+__global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
+  constexpr int BI = solve_bi(L3T, BLK);
+  constexpr int NL = 3 * BI;  // lines of one work-group: component-major
+  __shared__ cplx buf0[NL * L3T], buf1[NL * L3T];
+  const int groups_i = (S.L1 + BI - 1) / BI;
+  const int q = blockIdx.x / groups_i;
+  const int i0 = (blockIdx.x % groups_i) * BI;
+  const int bi = min(BI, S.L1 - i0);
+  const long kstride = (long)S.L1 * S.L2;
+  const long base = i0 + (long)S.L1 * q;
+  for (int w = threadIdx.x; w < NL * L3T; w += blockDim.x) {
+    const int y = w / NL;
+    const int rem = w - y * NL;
+    const int comp = rem / BI, di = rem - comp * BI;
+    if (di < bi)
+      buf0[(comp * BI + di) * L3T + y] =
+          cmul(S.data[comp * S.N + base + di + y * kstride], S.twist[y]);
+  }
+  __syncthreads();
+  cplx* f = fft_stages<L3T, 0, 1, -1>(S.roots, buf0, buf1, NL);
+  cplx* g = (f == buf0) ? buf1 : buf0;
+  const cplx Eb = S.e2[q];
+  if (!BLK) {
+    for (int w = threadIdx.x; w < bi * L3T; w += blockDim.x) {
+      const int di = w / L3T, r = w - di * L3T;
+      cplx bv[3], xv[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) bv[a] = f[(a * BI + di) * L3T + r];
+      mode_solve(S, S.e1[i0 + di], Eb, S.e3[r], bv, xv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) g[(a * BI + di) * L3T + r] = xv[a];
+    }
+  } else {
+    // sub-lattice p has offsets o2(p) = (a+p)&1, o3(p) = (a+c+p)&1
+    const int o20 = S.a & 1, o30 = (S.a + S.c) & 1;
+    for (int w = threadIdx.x; w < (bi / 2) * L3T; w += blockDim.x) {
+      const int dp = w / L3T, r = w - dp * L3T;
+      const int m1p = (i0 >> 1) + dp;
+      const cplx Ea = S.e1[m1p], Eg = S.e3[r];
+      // T_p = e^{-i(o2 beta + o3 gamma)}: conj(Eb)^o2 conj(Eg)^o3
+      const cplx cb = cconj(Eb), cg = cconj(Eg);
+      const cplx one = mk(1.0, 0.0);
+      const cplx T0 = cmul(o20 ? cb : one, o30 ? cg : one);
+      const cplx T1 = cmul(o20 ? one : cb, o30 ? one : cg);
+      const cplx t1e = cmulc(Ea, T1);  // T1 e^{-i alpha}
+      cplx c0[3], c1[3], z0[3], z1[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const cplx v0 = cmul(T0, f[(a * BI + 2 * dp) * L3T + r]);
+        const cplx v1 = cmul(t1e, f[(a * BI + 2 * dp + 1) * L3T + r]);
+        c0[a] = cadd(v0, v1);
+        c1[a] = csub(v0, v1);
+      }
+      mode_solve(S, Ea, Eb, Eg, c0, z0);
+      mode_solve(S, mk(-Ea.x, -Ea.y), Eb, Eg, c1, z1);  // m1 = m1' + n1/2: alpha + pi
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        g[(a * BI + 2 * dp) * L3T + r] = cmulc(T0, cadd(z0[a], z1[a]));
+        g[(a * BI + 2 * dp + 1) * L3T + r] = cmulc(t1e, csub(z0[a], z1[a]));
+      }
+    }
+  }
+  __syncthreads();
+  const cplx* res = fft_stages<L3T, 0, 1, +1>(S.roots, g, f, NL);
+  for (int w = threadIdx.x; w < NL * L3T; w += blockDim.x) {
+    const int y = w / NL;
+    const int rem = w - y * NL;
+    const int comp = rem / BI, di = rem - comp * BI;
+    if (di < bi)
+      S.data[comp * S.N + base + di + y * kstride] =
+          cmul(res[(comp * BI + di) * L3T + y], cconj(S.twist[y]));
+  }
+}
+
+__global__ void table_kernel(int L, double phi, int kind, cplx* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L) return;
   double ang;
   if (kind == 0)
-    ang = -(double)t * phi / (double)L;          // twist e^{-i x phi / L}
+    ang = -(double)t * phi / (double)L;              // twist e^{-i t phi / L}
   else if (kind == 1)
-    ang = -(phi + 2.0 * M_PI * t) / nfull;       // e^{-i beta_q}
+    ang = -2.0 * M_PI * (double)t / (double)L;       // roots e^{-2 pi i t / L}
   else
-    ang = -2.0 * M_PI * (double)t / (double)L;   // roots
+    ang = (phi + 2.0 * M_PI * (double)t) / (double)L;  // mode phase e^{i (phi + 2 pi t)/L}
   double s, c;
   sincos(ang, &s, &c);
   out[t] = mk(c, s);
 }
 
-int factorize(int L, int* fac) {
-  int n = 0;
-  while (L % 4 == 0) { fac[n++] = 4; L /= 4; }
-  while (L % 2 == 0) { fac[n++] = 2; L /= 2; }
-  while (L % 3 == 0) { fac[n++] = 3; L /= 3; }
-  return (L == 1) ? n : -1;
-}
-
+// Tables per layout: for each transform length Lt[l] (axis 0 of a block: n1/2)
+// the roots and the twist, and the mode phases e^{i(phi_l + 2 pi t)/n_l}.
 int ensure_tables(pbr_ctx* c, int block, const double kappa[3]) {
   FftTables& T = c->fft[block + 1];
-  const int L[3] = {c->n1, block < 0 ? c->n2 : c->n2 / 2, block < 0 ? c->n3 : c->n3 / 2};
+  const int Lt[3] = {block < 0 ? c->n1 : c->n1 / 2, block < 0 ? c->n2 : c->n2 / 2,
+                     block < 0 ? c->n3 : c->n3 / 2};
   const int nf[3] = {c->n1, c->n2, c->n3};
   for (int l = 0; l < 3; ++l) {
     if (!T.roots[l]) {
-      T.L[l] = L[l];
-      PBR_TRY(dev_alloc(c, (void**)&T.roots[l], sizeof(cplx) * L[l]));
-      PBR_TRY(dev_alloc(c, (void**)&T.twist[l], sizeof(cplx) * L[l]));
-      PBR_TRY(dev_alloc(c, (void**)&T.post[l], sizeof(cplx) * L[l]));
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(L[l], 256)), dim3(256), 0, c->stream, L[l],
-                         0.0, (double)nf[l], 2, T.roots[l]);
+      T.L[l] = Lt[l];
+      PBR_TRY(dev_alloc(c, (void**)&T.roots[l], sizeof(cplx) * Lt[l]));
+      PBR_TRY(dev_alloc(c, (void**)&T.twist[l], sizeof(cplx) * Lt[l]));
+      PBR_TRY(dev_alloc(c, (void**)&T.post[l], sizeof(cplx) * nf[l]));
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream, Lt[l],
+                         0.0, 1, T.roots[l]);
     }
   }
   if (T.kappa[0] != kappa[0] || T.kappa[1] != kappa[1] || T.kappa[2] != kappa[2]) {
     for (int l = 0; l < 3; ++l) {
       const double phi = 2.0 * M_PI * kappa[l];
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(L[l], 256)), dim3(256), 0, c->stream, L[l],
-                         phi, (double)nf[l], 0, T.twist[l]);
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(L[l], 256)), dim3(256), 0, c->stream, L[l],
-                         phi, (double)nf[l], 1, T.post[l]);
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream, Lt[l],
+                         phi, 0, T.twist[l]);
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream, nf[l],
+                         phi, 2, T.post[l]);
       T.kappa[l] = kappa[l];
     }
   }
@@ -340,59 +403,102 @@ int ensure_tables(pbr_ctx* c, int block, const double kappa[3]) {
   return ST_OK;
 }
 
-int run_axis(pbr_ctx* c, int block, int axis, int sign, const cplx* in, cplx* out, double scale) {
+// ---- launch helpers: one kernel instance per supported transform length ----
+#define PBR_FFT_LENGTHS(X) \
+  X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+typedef void (*LineKernel)(LineArgs);
+typedef void (*SolveKernel)(SolveArgs);
+
+template <int AXIS, int SPLIT, int SIGN>
+LineKernel line_kernel(int L) {
+  switch (L) {
+#define PBR_CASE(n) \
+  case n:           \
+    return fft_lines_kernel<n, AXIS, SPLIT, SIGN>;
+    PBR_FFT_LENGTHS(PBR_CASE)
+#undef PBR_CASE
+    default:
+      return nullptr;
+  }
+}
+
+template <int BLK>
+SolveKernel solve_kernel(int L) {
+  switch (L) {
+#define PBR_CASE(n) \
+  case n:           \
+    return fft_solve_kernel<n, BLK>;
+    PBR_FFT_LENGTHS(PBR_CASE)
+#undef PBR_CASE
+    default:
+      return nullptr;
+  }
+}
+
+int run_lines(pbr_ctx* c, int block, int axis, int sign, const cplx* in, cplx* out,
+              double scale) {
   FftTables& T = c->fft[block + 1];
   const long N = c->layout_nodes(block);
-  AxisArgs A;
-  A.L1 = T.L[0];
-  A.L2 = T.L[1];
-  A.L3 = T.L[2];
-  A.axis = axis;
-  A.L = T.L[axis];
-  A.nlines = N / A.L;
+  LineArgs A;
+  A.L1 = c->n1;
+  A.L2 = block < 0 ? c->n2 : c->n2 / 2;
+  A.L3 = block < 0 ? c->n3 : c->n3 / 2;
+  const int split = (axis == 0 && block >= 0) ? 1 : 0;
+  const int LT = T.L[axis];
+  const int LM = split ? 2 * LT : LT;
+  A.nlines = N / LM;
   A.N = N;
-  A.B = FFT_ELEMS / A.L;
-  if (A.B < 1) {
-    c->set_error("FFT line longer than the LDS batch");
-    return ST_EINVAL;
-  }
-  A.nfac = factorize(A.L, A.fac);
-  if (A.nfac < 0) {
-    c->set_error("FFT length must be of the form 2^a 3^b");
-    return ST_EINVAL;
-  }
-  A.sign = sign;
   A.roots = T.roots[axis];
+  A.twist = T.twist[axis];
   A.scale = scale;
   A.in = in;
   A.out = out;
-  const bool blocked = block >= 0;
-  const int a = block >> 1, cc = block & 1;
-  A.par_off = (axis == 1) ? a : (a + cc);
-  A.pre = nullptr;
-  A.post = nullptr;
-  A.pre_conj = 0;
-  A.post_conj = 0;
-  A.parity_mode = 0;
-  A.pre_is_parity = 0;
-  if (sign < 0) {
-    A.pre = T.twist[axis];
-    if (blocked && axis > 0) {
-      A.post = T.post[axis];
-      A.parity_mode = 1;
-    }
-  } else {
-    A.post = T.twist[axis];
-    A.post_conj = 1;
-    if (blocked && axis > 0) {
-      A.pre = T.post[axis];
-      A.pre_conj = 1;
-      A.pre_is_parity = 1;
-    }
+  LineKernel k = nullptr;
+  if (axis == 0 && split)
+    k = sign < 0 ? line_kernel<0, 1, -1>(LT) : line_kernel<0, 1, 1>(LT);
+  else if (axis == 0)
+    k = sign < 0 ? line_kernel<0, 0, -1>(LT) : line_kernel<0, 0, 1>(LT);
+  else
+    k = sign < 0 ? line_kernel<1, 0, -1>(LT) : line_kernel<1, 0, 1>(LT);
+  if (!k) {
+    c->set_error("FFT lengths must be 2^a 3^b up to 256 (blocks: 512 along i)");
+    return ST_EINVAL;
   }
-  dim3 grid(ceil_div(A.nlines, A.B), 3);
-  hipLaunchKernelGGL(fft_axis_kernel, grid, dim3(FFT_THREADS), 2 * FFT_ELEMS * sizeof(cplx),
-                     c->stream, A);
+  const int B = std::max(1, FFT_ELEMS / LM);
+  dim3 grid(ceil_div(A.nlines, B), 3);
+  hipLaunchKernelGGL(k, grid, dim3(FFT_THREADS), 0, c->stream, A);
+  PBR_HIP(c, hipGetLastError());
+  return ST_OK;
+}
+
+int run_solve(pbr_ctx* c, int block, double shift, cplx* z) {
+  FftTables& T = c->fft[block + 1];
+  SolveArgs S;
+  S.L1 = c->n1;
+  S.L2 = block < 0 ? c->n2 : c->n2 / 2;
+  S.L3 = block < 0 ? c->n3 : c->n3 / 2;
+  S.N = c->layout_nodes(block);
+  S.a = block >= 0 ? block >> 1 : 0;
+  S.c = block >= 0 ? block & 1 : 0;
+  S.roots = T.roots[2];
+  S.twist = T.twist[2];
+  S.e1 = T.post[0];
+  S.e2 = T.post[1];
+  S.e3 = T.post[2];
+  for (int m = 0; m < 3; ++m)
+    for (int d = 0; d < 5; ++d) S.cf[m][d] = c->cf[m][d];
+  for (int qq = 0; qq < 21; ++qq) S.Cref[qq] = c->Cref[qq];
+  S.shift_rho = shift * c->rho_ref;
+  S.data = z;
+  const SolveKernel k = block >= 0 ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
+  if (!k) {
+    c->set_error("FFT lengths must be 2^a 3^b up to 256");
+    return ST_EINVAL;
+  }
+  const int bi = solve_bi(S.L3, block >= 0 ? 1 : 0);
+  const int groups_i = (S.L1 + bi - 1) / bi;
+  hipLaunchKernelGGL(k, dim3((unsigned)(groups_i * S.L2)), dim3(FFT_THREADS), 0, c->stream, S);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
@@ -403,30 +509,10 @@ int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, c
                    cplx* z) {
   PBR_TRY(ensure_tables(c, block, kappa));
   const long N = c->layout_nodes(block);
-  // forward: y2, y3, then i (the block factors depend on i)
-  PBR_TRY(run_axis(c, block, 1, -1, r, z, 1.0));
-  PBR_TRY(run_axis(c, block, 2, -1, z, z, 1.0));
-  PBR_TRY(run_axis(c, block, 0, -1, z, z, 1.0));
-  SolveArgs S;
-  const FftTables& T = c->fft[block + 1];
-  S.L1 = T.L[0];
-  S.L2 = T.L[1];
-  S.L3 = T.L[2];
-  S.N = N;
-  const int nf[3] = {c->n1, c->n2, c->n3};
-  for (int l = 0; l < 3; ++l) {
-    S.th0[l] = 2.0 * M_PI * kappa[l] / nf[l];
-    S.dth[l] = 2.0 * M_PI / nf[l];
-  }
-  for (int m = 0; m < 3; ++m)
-    for (int d = 0; d < 5; ++d) S.cf[m][d] = c->cf[m][d];
-  for (int q = 0; q < 21; ++q) S.Cref[q] = c->Cref[q];
-  S.shift_rho = shift * c->rho_ref;
-  S.data = z;
-  hipLaunchKernelGGL(mode_solve_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, S);
-  PBR_HIP(c, hipGetLastError());
-  PBR_TRY(run_axis(c, block, 0, +1, z, z, 1.0));
-  PBR_TRY(run_axis(c, block, 2, +1, z, z, 1.0));
-  PBR_TRY(run_axis(c, block, 1, +1, z, z, 1.0 / (double)N));
+  PBR_TRY(run_lines(c, block, 0, -1, r, z, 1.0));
+  PBR_TRY(run_lines(c, block, 1, -1, z, z, 1.0));
+  PBR_TRY(run_solve(c, block, shift, z));
+  PBR_TRY(run_lines(c, block, 1, +1, z, z, 1.0));
+  PBR_TRY(run_lines(c, block, 0, +1, z, z, 1.0 / (double)N));
   return ST_OK;
 }
