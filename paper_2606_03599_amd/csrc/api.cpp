@@ -229,6 +229,16 @@ void pbr_destroy(pbr_ctx* c) {
     dev_free(W.st);
     dev_free(W.Wnull);
   }
+  for (auto& W : c->work)
+    if (W.hpin) (void)hipHostFree(W.hpin);
+  for (int b = 0; b < 4; ++b) {
+    if (c->bstream[b]) {
+      (void)hipStreamSynchronize(c->bstream[b]);
+      (void)hipStreamDestroy(c->bstream[b]);
+    }
+    if (c->join_ev[b]) (void)hipEventDestroy(c->join_ev[b]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   if (c->hpinned) (void)hipHostFree(c->hpinned);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;

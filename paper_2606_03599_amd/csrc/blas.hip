@@ -337,53 +337,53 @@ unsigned grid_for(long n) {
 
 #define LAUNCH(kern, grid, ...)                                                 \
   do {                                                                          \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(RT), 0, c->stream, __VA_ARGS__);   \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(RT), 0, st_, __VA_ARGS__);   \
     PBR_HIP(c, hipGetLastError());                                              \
   } while (0)
 
 int blas_part_capacity() { return 1024; }
 
-int vec_copy(pbr_ctx* c, long n, const cplx* a, cplx* b) {
+int vec_copy(pbr_ctx* c, hipStream_t st_, long n, const cplx* a, cplx* b) {
   LAUNCH(copy_kernel, grid_for(n), n, a, b);
   return ST_OK;
 }
-int vec_zero(pbr_ctx* c, long n, cplx* a) {
+int vec_zero(pbr_ctx* c, hipStream_t st_, long n, cplx* a) {
   LAUNCH(fill_zero_kernel, grid_for(n), n, a);
   return ST_OK;
 }
-int vec_scale(pbr_ctx* c, long n, cplx* a, double s) {
+int vec_scale(pbr_ctx* c, hipStream_t st_, long n, cplx* a, double s) {
   LAUNCH(scale_kernel, grid_for(n), n, a, s);
   return ST_OK;
 }
-int vec_diag_scale(pbr_ctx* c, long N, const double* d, const cplx* x, cplx* y) {
+int vec_diag_scale(pbr_ctx* c, hipStream_t st_, long N, const double* d, const cplx* x, cplx* y) {
   LAUNCH(diag_scale_kernel, grid_for(3 * N), N, d, x, y);
   return ST_OK;
 }
-int vec_resid(pbr_ctx* c, long N, double lam, const double* d, const cplx* u, const cplx* y,
+int vec_resid(pbr_ctx* c, hipStream_t st_, long N, double lam, const double* d, const cplx* u, const cplx* y,
               cplx* out) {
   LAUNCH(resid_kernel, grid_for(3 * N), N, lam, d, u, y, out);
   return ST_OK;
 }
-int vec_random(pbr_ctx* c, long n, unsigned long long seed, cplx* a) {
+int vec_random(pbr_ctx* c, hipStream_t st_, long n, unsigned long long seed, cplx* a) {
   LAUNCH(random_kernel, grid_for(n), n, seed, a);
   return ST_OK;
 }
 
-int dot_real_async(pbr_ctx* c, long n, const cplx* a, const cplx* b, double* part, double* out) {
+int dot_real_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* a, const cplx* b, double* part, double* out) {
   const unsigned g = grid_for(n);
   LAUNCH(dot_real_kernel, g, n, a, b, part, (const PcgScalars*)nullptr);
   LAUNCH(reduce_cols_kernel, 1, (int)g, 1, 1, (const double*)part, out);
   return ST_OK;
 }
 
-int dot_cplx_async(pbr_ctx* c, long n, const cplx* a, const cplx* b, double* part, double* out) {
+int dot_cplx_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* a, const cplx* b, double* part, double* out) {
   const unsigned g = grid_for(n);
   LAUNCH(dot_cplx_kernel, g, n, a, b, part);
   LAUNCH(reduce_cols_kernel, 1, (int)g, 2, 2, (const double*)part, out);
   return ST_OK;
 }
 
-int multi_dot_async(pbr_ctx* c, long n, int m, const cplx* U, long ld, const cplx* w, double* part,
+int multi_dot_async(pbr_ctx* c, hipStream_t st_, long n, int m, const cplx* U, long ld, const cplx* w, double* part,
                     double* out) {
   const unsigned g = grid_for(n) > 256 ? 256 : grid_for(n);
   LAUNCH(multi_dot_kernel, g, n, m, U, ld, w, part);
@@ -391,18 +391,18 @@ int multi_dot_async(pbr_ctx* c, long n, int m, const cplx* U, long ld, const cpl
   return ST_OK;
 }
 
-int gemv_sub(pbr_ctx* c, long n, int m, const cplx* U, long ld, const cplx* h, cplx* w) {
+int gemv_sub(pbr_ctx* c, hipStream_t st_, long n, int m, const cplx* U, long ld, const cplx* h, cplx* w) {
   LAUNCH(gemv_sub_kernel, grid_for(n), n, m, U, ld, h, w);
   return ST_OK;
 }
 
-int combine(pbr_ctx* c, long n, int m, int k, const cplx* U, long ld, const cplx* Y, cplx* V,
+int combine(pbr_ctx* c, hipStream_t st_, long n, int m, int k, const cplx* U, long ld, const cplx* Y, cplx* V,
             long ldv) {
   LAUNCH(combine_kernel, grid_for(n), n, m, k, U, ld, Y, V, ldv);
   return ST_OK;
 }
 
-int proj_gamma(pbr_ctx* c, long N, int nf, const double* W, cplx* v, double* part, double* coef) {
+int proj_gamma(pbr_ctx* c, hipStream_t st_, long N, int nf, const double* W, cplx* v, double* part, double* coef) {
   const unsigned g = grid_for(N) > 256 ? 256 : grid_for(N);
   LAUNCH(proj_dot_kernel, g, N, nf, W, (const cplx*)v, part);
   LAUNCH(reduce_cols_kernel, 1, (int)g, nf * 6, nf * 6, (const double*)part, coef);
@@ -410,7 +410,7 @@ int proj_gamma(pbr_ctx* c, long N, int nf, const double* W, cplx* v, double* par
   return ST_OK;
 }
 
-int pcg_init_async(pbr_ctx* c, long n, const cplx* r, const cplx* z, double tol, double* part,
+int pcg_init_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* r, const cplx* z, double tol, double* part,
                    double* part2, PcgScalars* st) {
   const unsigned g = grid_for(n);
   LAUNCH(dot_real_kernel, g, n, r, z, part, (const PcgScalars*)nullptr);
@@ -419,14 +419,14 @@ int pcg_init_async(pbr_ctx* c, long n, const cplx* r, const cplx* z, double tol,
   return ST_OK;
 }
 
-int pcg_alpha(pbr_ctx* c, long n, const cplx* p, const cplx* q, double* part, PcgScalars* st) {
+int pcg_alpha(pbr_ctx* c, hipStream_t st_, long n, const cplx* p, const cplx* q, double* part, PcgScalars* st) {
   const unsigned g = grid_for(n);
   LAUNCH(dot_real_kernel, g, n, p, q, part, (const PcgScalars*)st);
   LAUNCH(pcg_fin_alpha, 1, (int)g, (const double*)part, st);
   return ST_OK;
 }
 
-int pcg_xr(pbr_ctx* c, long n, cplx* x, cplx* r, const cplx* p, const cplx* q, double* part,
+int pcg_xr(pbr_ctx* c, hipStream_t st_, long n, cplx* x, cplx* r, const cplx* p, const cplx* q, double* part,
            PcgScalars* st) {
   const unsigned g = grid_for(n);
   LAUNCH(pcg_update_xr, g, n, x, r, p, q, part, (const PcgScalars*)st);
@@ -434,7 +434,7 @@ int pcg_xr(pbr_ctx* c, long n, cplx* x, cplx* r, const cplx* p, const cplx* q, d
   return ST_OK;
 }
 
-int pcg_beta_p(pbr_ctx* c, long n, const cplx* r, const cplx* z, cplx* p, double* part,
+int pcg_beta_p(pbr_ctx* c, hipStream_t st_, long n, const cplx* r, const cplx* z, cplx* p, double* part,
                PcgScalars* st) {
   const unsigned g = grid_for(n);
   LAUNCH(dot_real_kernel, g, n, r, z, part, (const PcgScalars*)st);

@@ -17,26 +17,26 @@ struct PcgScalars {
 };
 
 int blas_part_capacity();
-int vec_copy(pbr_ctx* c, long n, const cplx* a, cplx* b);
-int vec_zero(pbr_ctx* c, long n, cplx* a);
-int vec_scale(pbr_ctx* c, long n, cplx* a, double s);
-int vec_diag_scale(pbr_ctx* c, long N, const double* d, const cplx* x, cplx* y);
-int vec_resid(pbr_ctx* c, long N, double lam, const double* d, const cplx* u, const cplx* y,
+int vec_copy(pbr_ctx* c, hipStream_t st_, long n, const cplx* a, cplx* b);
+int vec_zero(pbr_ctx* c, hipStream_t st_, long n, cplx* a);
+int vec_scale(pbr_ctx* c, hipStream_t st_, long n, cplx* a, double s);
+int vec_diag_scale(pbr_ctx* c, hipStream_t st_, long N, const double* d, const cplx* x, cplx* y);
+int vec_resid(pbr_ctx* c, hipStream_t st_, long N, double lam, const double* d, const cplx* u, const cplx* y,
               cplx* out);
-int vec_random(pbr_ctx* c, long n, unsigned long long seed, cplx* a);
-int dot_real_async(pbr_ctx* c, long n, const cplx* a, const cplx* b, double* part, double* out);
-int dot_cplx_async(pbr_ctx* c, long n, const cplx* a, const cplx* b, double* part, double* out);
-int multi_dot_async(pbr_ctx* c, long n, int m, const cplx* U, long ld, const cplx* w,
+int vec_random(pbr_ctx* c, hipStream_t st_, long n, unsigned long long seed, cplx* a);
+int dot_real_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* a, const cplx* b, double* part, double* out);
+int dot_cplx_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* a, const cplx* b, double* part, double* out);
+int multi_dot_async(pbr_ctx* c, hipStream_t st_, long n, int m, const cplx* U, long ld, const cplx* w,
                     double* part, double* out);
-int gemv_sub(pbr_ctx* c, long n, int m, const cplx* U, long ld, const cplx* h, cplx* w);
-int combine(pbr_ctx* c, long n, int m, int k, const cplx* U, long ld, const cplx* Y, cplx* V,
+int gemv_sub(pbr_ctx* c, hipStream_t st_, long n, int m, const cplx* U, long ld, const cplx* h, cplx* w);
+int combine(pbr_ctx* c, hipStream_t st_, long n, int m, int k, const cplx* U, long ld, const cplx* Y, cplx* V,
             long ldv);
-int proj_gamma(pbr_ctx* c, long N, int nf, const double* W, cplx* v, double* part, double* coef);
+int proj_gamma(pbr_ctx* c, hipStream_t st_, long N, int nf, const double* W, cplx* v, double* part, double* coef);
 
-int pcg_init_async(pbr_ctx* c, long n, const cplx* r, const cplx* z, double tol, double* part,
+int pcg_init_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* r, const cplx* z, double tol, double* part,
                    double* part2, PcgScalars* st);
-int pcg_alpha(pbr_ctx* c, long n, const cplx* p, const cplx* q, double* part, PcgScalars* st);
-int pcg_xr(pbr_ctx* c, long n, cplx* x, cplx* r, const cplx* p, const cplx* q, double* part,
+int pcg_alpha(pbr_ctx* c, hipStream_t st_, long n, const cplx* p, const cplx* q, double* part, PcgScalars* st);
+int pcg_xr(pbr_ctx* c, hipStream_t st_, long n, cplx* x, cplx* r, const cplx* p, const cplx* q, double* part,
            PcgScalars* st);
-int pcg_beta_p(pbr_ctx* c, long n, const cplx* r, const cplx* z, cplx* p, double* part,
+int pcg_beta_p(pbr_ctx* c, hipStream_t st_, long n, const cplx* r, const cplx* z, cplx* p, double* part,
                PcgScalars* st);

@@ -3,6 +3,7 @@
 // used by the solver drivers.
 #pragma once
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,9 @@ struct LayoutWork {
   PcgScalars* st = nullptr;
   double* Wnull = nullptr;    // Gamma null fields (nf x N real, orthonormal after sqrt(rho))
   int nf = 0;
+  int block = -2;                // layout of this work area (-1 full, 0..3 blocks)
+  hipStream_t stream = nullptr;  // stream of this layout's work (null: the context stream)
+  double* hpin = nullptr;        // pinned host scratch of this layout (32768 doubles)
 };
 
 struct pbr_ctx {
@@ -67,11 +71,23 @@ struct pbr_ctx {
   LayoutWork work[5];
 
   double* hpinned = nullptr;      // pinned host scratch (4096 doubles)
+  // Streams of the four concurrent block solves (created on first use, default
+  // priority) and the events that fork them from / join them to `stream`.
+  hipStream_t bstream[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
   std::string err;
-  void set_error(const std::string& s) { err = s; }
+  std::mutex err_mu;
+  void set_error(const std::string& s) {
+    std::lock_guard<std::mutex> lk(err_mu);
+    err = s;
+  }
 
   DevMaterial& material(int block) { return mat[block + 1]; }
+  hipStream_t stream_of(int block) const {
+    return work[block + 1].stream ? work[block + 1].stream : stream;
+  }
   long layout_nodes(int block) const { return block < 0 ? n : n / 4; }
 };
 
@@ -84,11 +100,13 @@ int layout_scatter(pbr_ctx* c, int block, const cplx* blk, cplx* full);
 
 // Geometry of a layout at wave vector kappa.
 Geo make_geo(const pbr_ctx* c, int block, const double kappa[3]);
-// y = (A + s M) x in layout `block`
-int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y);
+// y = (A + s M) x in layout `block`; with `skip` (device int) non-null the
+// kernels return at once when *skip != 0 (a converged PCG's remaining iterations)
+int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
+                 const int* skip = nullptr);
 // z = preconditioner(r) in layout `block`
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
-                   const cplx* r, cplx* z);
+                   const cplx* r, cplx* z, const int* skip = nullptr);
 
 // solver drivers (solver.cpp)
 int ensure_work(pbr_ctx* c, int block);

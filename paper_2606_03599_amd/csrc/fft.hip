@@ -133,6 +133,7 @@ struct LineArgs {
   double scale;
   const cplx* in;
   cplx* out;
+  const int* skip;  // optional: the launch does nothing when *skip != 0
 };
 
 // LT: transform length; AXIS: 0 (memory-contiguous lines of length LM) or 1;
@@ -143,6 +144,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   constexpr int LM = SPLIT ? 2 * LT : LT;          // line length in memory
   constexpr int B = (FFT_ELEMS / LM) > 0 ? FFT_ELEMS / LM : 1;  // lines per work-group
   __shared__ cplx buf0[B * LM], buf1[B * LM];
+  if (A.skip && __atomic_load_n(A.skip, __ATOMIC_RELAXED)) return;
   const int comp = blockIdx.y;
   const long l0 = (long)blockIdx.x * B;
   const int nb = (int)min((long)B, A.nlines - l0);
@@ -208,6 +210,7 @@ struct SolveArgs {
   double Cref[21];
   double shift_rho;
   cplx* data;
+  const int* skip;  // optional: the launch does nothing when *skip != 0
 };
 
 // K(m)^-1 b for the mode whose one-step phases are Ea = e^{i alpha},
@@ -287,6 +290,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   constexpr int BI = solve_bi(L3T, BLK);
   constexpr int NL = 3 * BI;  // lines of one work-group: component-major
   __shared__ cplx buf0[NL * L3T], buf1[NL * L3T];
+  if (S.skip && __atomic_load_n(S.skip, __ATOMIC_RELAXED)) return;
   const int groups_i = (S.L1 + BI - 1) / BI;
   const int q = blockIdx.x / groups_i;
   const int i0 = (blockIdx.x % groups_i) * BI;
@@ -385,16 +389,16 @@ int ensure_tables(pbr_ctx* c, int block, const double kappa[3]) {
       PBR_TRY(dev_alloc(c, (void**)&T.roots[l], sizeof(cplx) * Lt[l]));
       PBR_TRY(dev_alloc(c, (void**)&T.twist[l], sizeof(cplx) * Lt[l]));
       PBR_TRY(dev_alloc(c, (void**)&T.post[l], sizeof(cplx) * nf[l]));
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream, Lt[l],
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream_of(block), Lt[l],
                          0.0, 1, T.roots[l]);
     }
   }
   if (T.kappa[0] != kappa[0] || T.kappa[1] != kappa[1] || T.kappa[2] != kappa[2]) {
     for (int l = 0; l < 3; ++l) {
       const double phi = 2.0 * M_PI * kappa[l];
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream, Lt[l],
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream_of(block), Lt[l],
                          phi, 0, T.twist[l]);
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream, nf[l],
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream_of(block), nf[l],
                          phi, 2, T.post[l]);
       T.kappa[l] = kappa[l];
     }
@@ -437,7 +441,7 @@ SolveKernel solve_kernel(int L) {
 }
 
 int run_lines(pbr_ctx* c, int block, int axis, int sign, const cplx* in, cplx* out,
-              double scale) {
+              double scale, const int* skip) {
   FftTables& T = c->fft[block + 1];
   const long N = c->layout_nodes(block);
   LineArgs A;
@@ -454,6 +458,7 @@ int run_lines(pbr_ctx* c, int block, int axis, int sign, const cplx* in, cplx* o
   A.scale = scale;
   A.in = in;
   A.out = out;
+  A.skip = skip;
   LineKernel k = nullptr;
   if (axis == 0 && split)
     k = sign < 0 ? line_kernel<0, 1, -1>(LT) : line_kernel<0, 1, 1>(LT);
@@ -467,12 +472,12 @@ int run_lines(pbr_ctx* c, int block, int axis, int sign, const cplx* in, cplx* o
   }
   const int B = std::max(1, FFT_ELEMS / LM);
   dim3 grid(ceil_div(A.nlines, B), 3);
-  hipLaunchKernelGGL(k, grid, dim3(FFT_THREADS), 0, c->stream, A);
+  hipLaunchKernelGGL(k, grid, dim3(FFT_THREADS), 0, c->stream_of(block), A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
 
-int run_solve(pbr_ctx* c, int block, double shift, cplx* z) {
+int run_solve(pbr_ctx* c, int block, double shift, cplx* z, const int* skip) {
   FftTables& T = c->fft[block + 1];
   SolveArgs S;
   S.L1 = c->n1;
@@ -491,6 +496,7 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z) {
   for (int qq = 0; qq < 21; ++qq) S.Cref[qq] = c->Cref[qq];
   S.shift_rho = shift * c->rho_ref;
   S.data = z;
+  S.skip = skip;
   const SolveKernel k = block >= 0 ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
   if (!k) {
     c->set_error("FFT lengths must be 2^a 3^b up to 256");
@@ -498,7 +504,8 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z) {
   }
   const int bi = solve_bi(S.L3, block >= 0 ? 1 : 0);
   const int groups_i = (S.L1 + bi - 1) / bi;
-  hipLaunchKernelGGL(k, dim3((unsigned)(groups_i * S.L2)), dim3(FFT_THREADS), 0, c->stream, S);
+  hipLaunchKernelGGL(k, dim3((unsigned)(groups_i * S.L2)), dim3(FFT_THREADS), 0,
+                     c->stream_of(block), S);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
@@ -506,13 +513,13 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z) {
 }  // namespace
 
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, const cplx* r,
-                   cplx* z) {
+                   cplx* z, const int* skip) {
   PBR_TRY(ensure_tables(c, block, kappa));
   const long N = c->layout_nodes(block);
-  PBR_TRY(run_lines(c, block, 0, -1, r, z, 1.0));
-  PBR_TRY(run_lines(c, block, 1, -1, z, z, 1.0));
-  PBR_TRY(run_solve(c, block, shift, z));
-  PBR_TRY(run_lines(c, block, 1, +1, z, z, 1.0));
-  PBR_TRY(run_lines(c, block, 0, +1, z, z, 1.0 / (double)N));
+  PBR_TRY(run_lines(c, block, 0, -1, r, z, 1.0, skip));
+  PBR_TRY(run_lines(c, block, 1, -1, z, z, 1.0, skip));
+  PBR_TRY(run_solve(c, block, shift, z, skip));
+  PBR_TRY(run_lines(c, block, 1, +1, z, z, 1.0, skip));
+  PBR_TRY(run_lines(c, block, 0, +1, z, z, 1.0 / (double)N, skip));
   return ST_OK;
 }

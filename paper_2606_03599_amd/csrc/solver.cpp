@@ -13,6 +13,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "../../include/pbr_host.h"
@@ -45,28 +46,28 @@ bool is_gamma(const double k[3]) {
   return true;
 }
 
-// Read `count` doubles from device to host (synchronises the stream).
-int readback(pbr_ctx* c, const double* dev, double* host, int count) {
-  PBR_HIP(c, hipMemcpyAsync(c->hpinned, dev, sizeof(double) * count, hipMemcpyDeviceToHost,
-                            c->stream));
-  PBR_HIP(c, hipStreamSynchronize(c->stream));
-  for (int i = 0; i < count; ++i) host[i] = c->hpinned[i];
+// Read `count` doubles from device to host (synchronises the layout's stream).
+int readback(pbr_ctx* c, LayoutWork& W, const double* dev, double* host, int count) {
+  const hipStream_t SO = c->stream_of(W.block);
+  PBR_HIP(c, hipMemcpyAsync(W.hpin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, SO));
+  PBR_HIP(c, hipStreamSynchronize(SO));
+  for (int i = 0; i < count; ++i) host[i] = W.hpin[i];
   return ST_OK;
 }
 
-int upload_small(pbr_ctx* c, cplx* dev, const std::vector<zc>& h) {
+int upload_small(pbr_ctx* c, LayoutWork& W, cplx* dev, const std::vector<zc>& h) {
   if ((long)h.size() > SMALL_CPLX) {
     c->set_error("Krylov basis too large for the small-matrix buffer");
     return ST_EINVAL;
   }
+  const hipStream_t SO = c->stream_of(W.block);
   for (size_t i = 0; i < h.size(); ++i) {
-    c->hpinned[2 * i] = h[i].real();
-    c->hpinned[2 * i + 1] = h[i].imag();
+    W.hpin[2 * i] = h[i].real();
+    W.hpin[2 * i + 1] = h[i].imag();
   }
-  PBR_HIP(c, hipMemcpyAsync(dev, c->hpinned, sizeof(cplx) * h.size(), hipMemcpyHostToDevice,
-                            c->stream));
+  PBR_HIP(c, hipMemcpyAsync(dev, W.hpin, sizeof(cplx) * h.size(), hipMemcpyHostToDevice, SO));
   // the pinned staging buffer is reused by the next call: wait for the copy
-  PBR_HIP(c, hipStreamSynchronize(c->stream));
+  PBR_HIP(c, hipStreamSynchronize(SO));
   return ST_OK;
 }
 
@@ -156,21 +157,22 @@ int ensure_null_fields(pbr_ctx* c, int block) {
     for (long t = 0; t < N; ++t) F[t] = std::sqrt(rho[t] / sr);
   }
   PBR_TRY(dev_alloc(c, (void**)&W.Wnull, sizeof(double) * nf * N));
+  const hipStream_t SO = c->stream_of(block);
   PBR_HIP(c, hipMemcpyAsync(W.Wnull, F.data(), sizeof(double) * nf * N, hipMemcpyHostToDevice,
-                            c->stream));
-  PBR_HIP(c, hipStreamSynchronize(c->stream));
+                            SO));
+  PBR_HIP(c, hipStreamSynchronize(SO));
   W.nf = nf;
   return ST_OK;
 }
 
 int project_null(pbr_ctx* c, LayoutWork& W, cplx* v) {
-  return proj_gamma(c, W.N, W.nf, W.Wnull, v, W.part, W.dscal);
+  return proj_gamma(c, c->stream_of(W.block), W.N, W.nf, W.Wnull, v, W.part, W.dscal);
 }
 
 double vnorm(pbr_ctx* c, LayoutWork& W, const cplx* v, int* status) {
   double h;
-  int s = dot_real_async(c, 3 * W.N, v, v, W.part, W.dscal);
-  if (s == ST_OK) s = readback(c, W.dscal, &h, 1);
+  int s = dot_real_async(c, c->stream_of(W.block), 3 * W.N, v, v, W.part, W.dscal);
+  if (s == ST_OK) s = readback(c, W, W.dscal, &h, 1);
   *status = s;
   return std::sqrt(std::max(h, 0.0));
 }
@@ -182,6 +184,7 @@ int ensure_work(pbr_ctx* c, int block) {
   const long N = c->layout_nodes(block);
   if (W.N == N && W.x) return ST_OK;
   W.N = N;
+  W.block = block;
   const long n3 = 3 * N;
   PBR_TRY(alloc_vec(c, &W.x, n3));
   PBR_TRY(alloc_vec(c, &W.r, n3));
@@ -196,6 +199,7 @@ int ensure_work(pbr_ctx* c, int block) {
   PBR_TRY(dev_alloc(c, (void**)&W.part2, sizeof(double) * 1024 * 2));
   PBR_TRY(dev_alloc(c, (void**)&W.dscal, sizeof(double) * 4096));
   PBR_TRY(dev_alloc(c, (void**)&W.st, sizeof(PcgScalars)));
+  if (!W.hpin) PBR_HIP(c, hipHostMalloc((void**)&W.hpin, sizeof(double) * 32768));
   return ST_OK;
 }
 
@@ -203,16 +207,17 @@ int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const 
               const pbr_opts& o, int* iters, int* conv) {
   PBR_TRY(ensure_work(c, block));
   LayoutWork& W = c->work[block + 1];
+  const hipStream_t SO = c->stream_of(block);
   const long n3 = 3 * W.N;
   const Geo g = make_geo(c, block, kappa);
-  PBR_TRY(vec_zero(c, n3, x));
-  PBR_TRY(vec_copy(c, n3, b, W.r));
+  PBR_TRY(vec_zero(c, SO, n3, x));
+  PBR_TRY(vec_copy(c, SO, n3, b, W.r));
   if (o.precond)
     PBR_TRY(launch_precond(c, kappa, block, shift, W.r, W.z));
   else
-    PBR_TRY(vec_copy(c, n3, W.r, W.z));
-  PBR_TRY(vec_copy(c, n3, W.z, W.p));
-  PBR_TRY(pcg_init_async(c, n3, W.r, W.z, o.tol_inner, W.part, W.part2, W.st));
+    PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
+  PBR_TRY(vec_copy(c, SO, n3, W.z, W.p));
+  PBR_TRY(pcg_init_async(c, SO, n3, W.r, W.z, o.tol_inner, W.part, W.part2, W.st));
   const int chunk_auto = 10;
   const int chunk = o.check_every > 0 ? o.check_every : chunk_auto;
   int done_iters = 0;
@@ -220,28 +225,27 @@ int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const 
   for (;;) {
     const int todo = std::min(chunk, o.maxit_inner - done_iters);
     if (todo <= 0) break;
+    const int* skip = &W.st->done;  // later launches of a converged chunk are no-ops
     for (int it = 0; it < todo; ++it) {
-      PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q));
-      PBR_TRY(pcg_alpha(c, n3, W.p, W.q, W.part, W.st));
-      PBR_TRY(pcg_xr(c, n3, x, W.r, W.p, W.q, W.part, W.st));
+      PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q, skip));
+      PBR_TRY(pcg_alpha(c, SO, n3, W.p, W.q, W.part, W.st));
+      PBR_TRY(pcg_xr(c, SO, n3, x, W.r, W.p, W.q, W.part, W.st));
       if (o.precond)
-        PBR_TRY(launch_precond(c, kappa, block, shift, W.r, W.z));
+        PBR_TRY(launch_precond(c, kappa, block, shift, W.r, W.z, skip));
       else
-        PBR_TRY(vec_copy(c, n3, W.r, W.z));
-      PBR_TRY(pcg_beta_p(c, n3, W.r, W.z, W.p, W.part, W.st));
+        PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
+      PBR_TRY(pcg_beta_p(c, SO, n3, W.r, W.z, W.p, W.part, W.st));
     }
-    PBR_HIP(c, hipMemcpyAsync(c->hpinned, W.st, sizeof(PcgScalars), hipMemcpyDeviceToHost,
-                              c->stream));
-    PBR_HIP(c, hipStreamSynchronize(c->stream));
-    std::memcpy(&hs, c->hpinned, sizeof(PcgScalars));
+    PBR_HIP(c, hipMemcpyAsync(W.hpin, W.st, sizeof(PcgScalars), hipMemcpyDeviceToHost, SO));
+    PBR_HIP(c, hipStreamSynchronize(SO));
+    std::memcpy(&hs, W.hpin, sizeof(PcgScalars));
     done_iters = hs.iters;
     if (hs.done) break;
   }
   // final state
-  PBR_HIP(c, hipMemcpyAsync(c->hpinned, W.st, sizeof(PcgScalars), hipMemcpyDeviceToHost,
-                            c->stream));
-  PBR_HIP(c, hipStreamSynchronize(c->stream));
-  std::memcpy(&hs, c->hpinned, sizeof(PcgScalars));
+  PBR_HIP(c, hipMemcpyAsync(W.hpin, W.st, sizeof(PcgScalars), hipMemcpyDeviceToHost, SO));
+  PBR_HIP(c, hipStreamSynchronize(SO));
+  std::memcpy(&hs, W.hpin, sizeof(PcgScalars));
   *iters = hs.iters;
   *conv = (hs.done == 1) ? 1 : 0;
   if (hs.done == 2) {
@@ -262,7 +266,8 @@ int op_apply(pbr_ctx* c, int block, const double kappa[3], double shift, const p
              const cplx* u, cplx* w, OpCounters& cnt) {
   LayoutWork& W = c->work[block + 1];
   DevMaterial& M = c->material(block);
-  PBR_TRY(vec_diag_scale(c, W.N, M.srho, u, W.b));
+  const hipStream_t SO = c->stream_of(block);
+  PBR_TRY(vec_diag_scale(c, SO, W.N, M.srho, u, W.b));
   int it = 0, conv = 0;
   int s = pcg_solve(c, block, kappa, shift, W.b, W.t, o, &it, &conv);
   if (s != ST_OK && s != ST_ENOCONV) return s;
@@ -271,7 +276,7 @@ int op_apply(pbr_ctx* c, int block, const double kappa[3], double shift, const p
   cnt.pcg_max = std::max(cnt.pcg_max, it);
   cnt.matvecs += it;
   if (!conv) cnt.pcg_fail += 1;
-  PBR_TRY(vec_diag_scale(c, W.N, M.srho, W.t, w));
+  PBR_TRY(vec_diag_scale(c, SO, W.N, M.srho, W.t, w));
   return ST_OK;
 }
 
@@ -283,6 +288,7 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
   PBR_TRY(ensure_work(c, block));
   LayoutWork& W = c->work[block + 1];
   DevMaterial& M = c->material(block);
+  const hipStream_t SO = c->stream_of(block);
   const long N = W.N, n3 = 3 * N;
   const bool gamma = is_gamma(kappa);
   int n_zero = 0;
@@ -307,11 +313,11 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
   OpCounters cnt;
   int st_err;
   // start vector
-  PBR_TRY(vec_random(c, n3, (unsigned long long)(o.seed * 7919 + 17 + block), W.U));
+  PBR_TRY(vec_random(c, SO, n3, (unsigned long long)(o.seed * 7919 + 17 + block), W.U));
   if (gamma) PBR_TRY(project_null(c, W, W.U));
   double nrm = vnorm(c, W, W.U, &st_err);
   PBR_TRY(st_err);
-  PBR_TRY(vec_scale(c, n3, W.U, 1.0 / nrm));
+  PBR_TRY(vec_scale(c, SO, n3, W.U, 1.0 / nrm));
 
   std::vector<zc> H((size_t)m * m, zc(0, 0));  // column-major
   std::vector<double> beta(m, 0.0);
@@ -331,15 +337,15 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
       // classical Gram-Schmidt, twice
       std::vector<zc> h(j + 1, zc(0, 0));
       for (int pass = 0; pass < 2; ++pass) {
-        PBR_TRY(multi_dot_async(c, n3, j + 1, W.U, ld, W.w, W.part, W.dscal));
-        PBR_TRY(readback(c, W.dscal, hbuf.data(), 2 * (j + 1)));
+        PBR_TRY(multi_dot_async(c, SO, n3, j + 1, W.U, ld, W.w, W.part, W.dscal));
+        PBR_TRY(readback(c, W, W.dscal, hbuf.data(), 2 * (j + 1)));
         std::vector<zc> hp(j + 1);
         for (int i = 0; i <= j; ++i) {
           hp[i] = zc(hbuf[2 * i], hbuf[2 * i + 1]);
           h[i] += hp[i];
         }
-        PBR_TRY(upload_small(c, W.small, hp));
-        PBR_TRY(gemv_sub(c, n3, j + 1, W.U, ld, W.small, W.w));
+        PBR_TRY(upload_small(c, W, W.small, hp));
+        PBR_TRY(gemv_sub(c, SO, n3, j + 1, W.U, ld, W.small, W.w));
       }
       if (gamma) PBR_TRY(project_null(c, W, W.w));
       const double b = vnorm(c, W, W.w, &st_err);
@@ -356,8 +362,8 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
       }
       cplx* un = W.U + (long)(j + 1) * ld;
       if (b > 1e-14 * std::abs(h[j]) && b > 0.0) {
-        PBR_TRY(vec_copy(c, n3, W.w, un));
-        PBR_TRY(vec_scale(c, n3, un, 1.0 / b));
+        PBR_TRY(vec_copy(c, SO, n3, W.w, un));
+        PBR_TRY(vec_scale(c, SO, n3, un, 1.0 / b));
       } else {
         // invariant subspace: the Ritz values of H are exact
         beta[j] = 0.0;
@@ -412,9 +418,9 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
         const int col = order[cc];
         Yk[(size_t)cc * m + r] = zc(Yr[2 * ((size_t)col * m + r)], Yr[2 * ((size_t)col * m + r) + 1]);
       }
-    PBR_TRY(upload_small(c, W.small, Yk));
-    PBR_TRY(combine(c, n3, m, kk, W.U, ld, W.small, W.U2, ld));
-    PBR_TRY(vec_copy(c, n3, W.U + (long)m * ld, W.U2 + (long)kk * ld));
+    PBR_TRY(upload_small(c, W, W.small, Yk));
+    PBR_TRY(combine(c, SO, n3, m, kk, W.U, ld, W.small, W.U2, ld));
+    PBR_TRY(vec_copy(c, SO, n3, W.U + (long)m * ld, W.U2 + (long)kk * ld));
     std::swap(W.U, W.U2);
     std::fill(H.begin(), H.end(), zc(0, 0));
     for (int i = 0; i < kk; ++i) H[(size_t)i * m + i] = theta[order[i]];
@@ -429,8 +435,8 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
       const int col = order[cc];
       Yk[(size_t)cc * m + r] = zc(Yr[2 * ((size_t)col * m + r)], Yr[2 * ((size_t)col * m + r) + 1]);
     }
-  PBR_TRY(upload_small(c, W.small, Yk));
-  PBR_TRY(combine(c, n3, m, nout, W.U, ld, W.small, W.U2, ld));
+  PBR_TRY(upload_small(c, W, W.small, Yk));
+  PBR_TRY(combine(c, SO, n3, m, nout, W.U, ld, W.small, W.U2, ld));
   // final Rayleigh quotients and residuals with the exact operator
   const Geo g = make_geo(c, block, kappa);
   std::vector<std::pair<double, int>> lam(nout);
@@ -439,33 +445,33 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
     cplx* u = W.U2 + (long)i * ld;
     if (gamma) PBR_TRY(project_null(c, W, u));
     // v = M^{-1/2} u  -> W.t ;  y = A v -> W.q
-    PBR_TRY(vec_diag_scale(c, N, M.isrho, u, W.t));
+    PBR_TRY(vec_diag_scale(c, SO, N, M.isrho, u, W.t));
     PBR_TRY(launch_apply(c, g, block, 0.0, W.t, W.q));
     cnt.matvecs += 1;
     double vals[3];
-    PBR_TRY(dot_real_async(c, n3, W.t, W.q, W.part, W.dscal));       // v^H A v
-    PBR_TRY(dot_real_async(c, n3, u, u, W.part, W.dscal + 1));        // v^H M v
-    PBR_TRY(dot_real_async(c, n3, W.q, W.q, W.part, W.dscal + 2));    // |Av|^2
-    PBR_TRY(readback(c, W.dscal, vals, 3));
+    PBR_TRY(dot_real_async(c, SO, n3, W.t, W.q, W.part, W.dscal));       // v^H A v
+    PBR_TRY(dot_real_async(c, SO, n3, u, u, W.part, W.dscal + 1));        // v^H M v
+    PBR_TRY(dot_real_async(c, SO, n3, W.q, W.q, W.part, W.dscal + 2));    // |Av|^2
+    PBR_TRY(readback(c, W, W.dscal, vals, 3));
     const double l = vals[0] / vals[1];
     // r = A v - l M v = y - l * srho .* u
-    PBR_TRY(vec_resid(c, N, l, M.srho, u, W.q, W.z));
+    PBR_TRY(vec_resid(c, SO, N, l, M.srho, u, W.q, W.z));
     double rr;
-    PBR_TRY(dot_real_async(c, n3, W.z, W.z, W.part, W.dscal));
-    PBR_TRY(readback(c, W.dscal, &rr, 1));
+    PBR_TRY(dot_real_async(c, SO, n3, W.z, W.z, W.part, W.dscal));
+    PBR_TRY(readback(c, W, W.dscal, &rr, 1));
     // |M v| = |srho .* u|
-    PBR_TRY(vec_diag_scale(c, N, M.srho, u, W.z));
+    PBR_TRY(vec_diag_scale(c, SO, N, M.srho, u, W.z));
     double mv;
-    PBR_TRY(dot_real_async(c, n3, W.z, W.z, W.part, W.dscal));
-    PBR_TRY(readback(c, W.dscal, &mv, 1));
+    PBR_TRY(dot_real_async(c, SO, n3, W.z, W.z, W.part, W.dscal));
+    PBR_TRY(readback(c, W, W.dscal, &mv, 1));
     const double denom = std::sqrt(vals[2]) + std::fabs(l) * std::sqrt(mv);
     const double rel = denom > 0 ? std::sqrt(rr) / denom : 0.0;
     max_res = std::max(max_res, rel);
     lam[i] = {l, i};
     if (evecs_dev) {
       // M-normalised eigenvector: v / sqrt(v^H M v)
-      PBR_TRY(vec_copy(c, n3, W.t, evecs_dev + (long)i * n3));
-      PBR_TRY(vec_scale(c, n3, evecs_dev + (long)i * n3, 1.0 / std::sqrt(vals[1])));
+      PBR_TRY(vec_copy(c, SO, n3, W.t, evecs_dev + (long)i * n3));
+      PBR_TRY(vec_scale(c, SO, n3, evecs_dev + (long)i * n3, 1.0 / std::sqrt(vals[1])));
     }
   }
   std::sort(lam.begin(), lam.end());
@@ -476,12 +482,12 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
     for (int i = 0; i < nout; ++i) sorted = sorted && lam[i].second == i;
     if (!sorted) {
       for (int i = 0; i < nout; ++i)
-        PBR_TRY(vec_copy(c, n3, evecs_dev + (long)lam[i].second * n3, W.U2 + (long)i * ld));
+        PBR_TRY(vec_copy(c, SO, n3, evecs_dev + (long)lam[i].second * n3, W.U2 + (long)i * ld));
       for (int i = 0; i < nout; ++i)
-        PBR_TRY(vec_copy(c, n3, W.U2 + (long)i * ld, evecs_dev + (long)i * n3));
+        PBR_TRY(vec_copy(c, SO, n3, W.U2 + (long)i * ld, evecs_dev + (long)i * n3));
     }
   }
-  PBR_HIP(c, hipStreamSynchronize(c->stream));
+  PBR_HIP(c, hipStreamSynchronize(SO));
   if (st) {
     st->outer_iters += restarts;
     st->op_applies += cnt.applies;
@@ -501,6 +507,80 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
   return ST_OK;
 }
 
+namespace {
+
+// Streams and events of the concurrent block solves (created once per context).
+int ensure_block_streams(pbr_ctx* c) {
+  for (int b = 0; b < 4; ++b) {
+    if (!c->bstream[b]) PBR_HIP(c, hipStreamCreateWithFlags(&c->bstream[b], hipStreamNonBlocking));
+    if (!c->join_ev[b])
+      PBR_HIP(c, hipEventCreateWithFlags(&c->join_ev[b], hipEventDisableTiming));
+  }
+  if (!c->fork_ev) PBR_HIP(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  return ST_OK;
+}
+
+void add_stats(pbr_stats* acc, const pbr_stats& one) {
+  acc->outer_iters += one.outer_iters;
+  acc->op_applies += one.op_applies;
+  acc->pcg_iters_total += one.pcg_iters_total;
+  acc->pcg_iters_max = std::max(acc->pcg_iters_max, one.pcg_iters_max);
+  acc->matvecs += one.matvecs;
+  acc->n_zero += one.n_zero;
+  acc->converged += one.converged;
+  acc->max_rel_resid = std::max(acc->max_rel_resid, one.max_rel_resid);
+  acc->pcg_avg = acc->op_applies ? (double)acc->pcg_iters_total / acc->op_applies : 0.0;
+}
+
+// Solve the blocks in `mask` concurrently: one host thread and one stream per
+// block (the blocks share nothing but the read-only context data).  The block
+// streams are ordered after everything already queued on the context stream, and
+// the context stream after them on return.
+int solve_blocks(pbr_ctx* c, const double kappa[3], int mask, const int nev_b[4], double shift,
+                 const pbr_opts& o, std::vector<double>* vals, pbr_stats* st) {
+  PBR_TRY(ensure_block_streams(c));
+  for (int b = 0; b < 4; ++b)
+    if (mask & (1 << b)) PBR_TRY(ensure_work(c, b));
+  PBR_HIP(c, hipEventRecord(c->fork_ev, c->stream));
+  int rc[4] = {ST_OK, ST_OK, ST_OK, ST_OK};
+  pbr_stats part[4];
+  std::memset(part, 0, sizeof(part));
+  std::vector<std::thread> th;
+  for (int b = 0; b < 4; ++b) {
+    if (!(mask & (1 << b))) continue;
+    vals[b].assign(nev_b[b], 0.0);
+    th.emplace_back([&, b]() {
+      if (hipSetDevice(c->device) != hipSuccess ||
+          hipStreamWaitEvent(c->bstream[b], c->fork_ev, 0) != hipSuccess) {
+        c->set_error("could not start a block solve on its stream");
+        rc[b] = ST_EDEVICE;
+        return;
+      }
+      c->work[b + 1].stream = c->bstream[b];
+      rc[b] = lanczos_eigs(c, kappa, b, nev_b[b], shift, o, vals[b].data(), nullptr, &part[b]);
+      if (hipEventRecord(c->join_ev[b], c->bstream[b]) != hipSuccess) rc[b] = ST_EDEVICE;
+      c->work[b + 1].stream = nullptr;
+    });
+  }
+  for (auto& t : th) t.join();
+  for (int b = 0; b < 4; ++b)
+    if (mask & (1 << b)) PBR_HIP(c, hipStreamWaitEvent(c->stream, c->join_ev[b], 0));
+  int status = ST_OK;
+  for (int b = 0; b < 4; ++b) {
+    if (!(mask & (1 << b))) continue;
+    if (st) add_stats(st, part[b]);
+    if (rc[b] == ST_ENOCONV && status == ST_OK) status = ST_ENOCONV;
+    if (rc[b] != ST_OK && rc[b] != ST_ENOCONV) status = rc[b];
+  }
+  return status;
+}
+
+}  // namespace
+
+// Lowest nev eigenvalues of the full pencil from the four blocks (Corollary 4.2):
+// each block is asked for nev/4 + 4 values; a block whose largest computed value
+// lies below the merged nev-th value may hide smaller ones that were not computed,
+// so it is solved again with more values until no block is flagged.
 int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const pbr_opts& o,
                 double* evals, pbr_stats* st) {
   int nev_b[4];
@@ -512,15 +592,11 @@ int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const 
   int need = 0xF;
   int status = ST_OK;
   for (int round = 0; round < 8 && need; ++round) {
-    for (int b = 0; b < 4; ++b) {
-      if (!(need & (1 << b))) continue;
-      vals[b].assign(nev_b[b], 0.0);
-      int s = lanczos_eigs(c, kappa, b, nev_b[b], shift, o, vals[b].data(), nullptr, st);
-      if (s == ST_ENOCONV)
-        status = ST_ENOCONV;
-      else if (s != ST_OK)
-        return s;
-    }
+    const int s = solve_blocks(c, kappa, need, nev_b, shift, o, vals, st);
+    if (s == ST_ENOCONV)
+      status = ST_ENOCONV;
+    else if (s != ST_OK)
+      return s;
     const double* vp[4] = {vals[0].data(), vals[1].data(), vals[2].data(), vals[3].data()};
     std::vector<double> merged(nev);
     const int mask = pbr_host_merge(nev, nev_b, vp, merged.data());

@@ -46,6 +46,7 @@ struct ApplyArgs {
   cplx* y;
   const double* C;
   const double* rho;
+  const int* skip;    // optional: the launch does nothing when *skip != 0
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -191,6 +192,7 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   static_assert(NH <= 64, "tau ring must fit in one wave");
   __shared__ cplx tau_s[6 * NP];
   __shared__ cplx x_s[3][3 * NX];
+  if (A.skip && __atomic_load_n(A.skip, __ATOMIC_RELAXED)) return;  // whole work-group
   const Geo& g = A.g;
   const int L1 = g.L1, L2 = g.L2, L3 = g.L3;
   const int N = A.N;
@@ -428,7 +430,8 @@ constexpr int TILE_I = 16, TILE_J = 16;
 
 }  // namespace
 
-int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y) {
+int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
+                 const int* skip) {
   DevMaterial& M = c->material(block);
   if (M.N * 168L >= (1L << 31)) {
     c->set_error("grid too large for 32-bit buffer offsets of the stencil kernel");
@@ -442,6 +445,7 @@ int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, c
   A.y = y;
   A.C = M.C;
   A.rho = M.rho;
+  A.skip = skip;
   A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
   A.tiles_j = (g.L2 + TILE_J - 1) / TILE_J;
   // chunk length: about one work-group per CU (256 CUs); longer chunks amortise
@@ -454,7 +458,7 @@ int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, c
   const int nchunks = (g.L3 + chunk - 1) / chunk;
   const unsigned grid = (unsigned)(tiles * nchunks);
   hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
-                     dim3(TILE_I * TILE_J + 64), 0, c->stream, A);
+                     dim3(TILE_I * TILE_J + 64), 0, c->stream_of(block), A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
