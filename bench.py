@@ -8,16 +8,19 @@ SPD stiffness (rho = 4); 16 points on the Gamma-X-M-Gamma-R path; the 20 lowest
 eigenpairs per point; shift delta = 0.30 C_max; tolerances 1e-12.
 
 One step = the whole hot path over the path: at every k, four parity-block
-shift-invert Krylov solves (inner PCG with the FFT-diagonal preconditioner, the
-fused stencil matvec, Gamma projection) merged with certification.  K steps are
-timed with a device synchronisation on both sides.  The full-space path (one
-solve of 3n unknowns per k) is run once afterwards for the comparison.
+shift-invert Krylov solves (run concurrently on four streams; inner PCG with the
+FFT-diagonal preconditioner, the fused stencil matvec, Gamma projection) merged
+with certification.  K steps are timed with a device synchronisation on both
+sides.  The full-space form (one solve of 3n^3 unknowns per k) is then compared
+with the blocked form on every fourth path point (--full-every), same GPU, same
+tolerances.
 
-Also measured live: the fused block matvec (A + delta M) x at n (4 blocks in
-rotation, HIP events on the context stream), reported against the MI355X HBM
-peak as the roofline of the dominant kernel, and the oracle (CPU) cost of the
-same path estimated from a bounded sample (one oracle matvec + preconditioner
-application at the same n, scaled by the GPU run's PCG iteration count).
+Also measured live: the fused block matvec (A + delta M) x at n (launches rotate
+through the 4 blocks, HIP events on the context stream), reported against the
+MI355X HBM peak as the roofline of the dominant kernel; the full-space matvec and
+the block preconditioner beside it; and the oracle (CPU) cost of the same path
+estimated from a bounded sample (one oracle matvec + preconditioner application
+at the same n, single-threaded, scaled by the GPU run's PCG iteration count).
 """
 
 import argparse
@@ -31,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = 48 + 168 + 8 + 48   # x, C (21 doubles), rho, y
+PRECOND_BYTES_PER_NODE = 48 + 48     # r in, z out
 
 
 def parse():
@@ -41,11 +45,16 @@ def parse():
     p.add_argument("--n", type=int, default=128)
     p.add_argument("--nk", type=int, default=16)
     p.add_argument("--nev", type=int, default=20)
-    p.add_argument("--no-full", action="store_true", help="skip the full-space comparison")
+    p.add_argument("--first", type=int, default=0,
+                   help="time only the first m points of the path (short profiled runs)")
+    p.add_argument("--full-every", type=int, default=4,
+                   help="compare with the full space on every k-th path point (0: skip)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     p.add_argument("--matvec-only", action="store_true",
                    help="only the matvec timing (for hardware-counter runs)")
     p.add_argument("--mv-iters", type=int, default=100)
+    p.add_argument("--serial-blocks", action="store_true",
+                   help="solve the four blocks one after another on one stream")
     return p.parse_args()
 
 
@@ -53,27 +62,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def matvec_timing(torch, ctx, n, kappa, delta, iters, blocks=(0, 1, 2, 3)):
-    """Average duration (s) of one (A + delta M) x launch per layout."""
+def kernel_timing(torch, ctx, n, kappa, delta, iters, blocks, op):
+    """Average duration (s) of one launch of `op` ("apply": the fused matvec
+    (A + delta M) x; "precond": the FFT preconditioner) over `iters` launches that
+    rotate through `blocks`, so that consecutive launches touch different data and
+    the 256 MB last-level cache cannot serve a repeated block.  HIP events are
+    recorded on torch's current stream, which is the stream the context launches
+    on."""
     from synth import complex_gaussian
-    out = {}
+    xs, ys = [], []
     for blk in blocks:
         N = n ** 3 if blk < 0 else n ** 3 // 4
-        x = torch.from_numpy(complex_gaussian(3 * N, seed=12345)).cuda()
-        y = torch.zeros_like(x)
-        for _ in range(10):
-            ctx.apply(kappa, blk, delta, x, y)
-        s = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        s.record()
-        for _ in range(iters):
-            ctx.apply(kappa, blk, delta, x, y)
-        e.record()
-        torch.cuda.synchronize()
-        out[blk] = s.elapsed_time(e) / 1e3 / iters
-        del x, y
-    return out
+        xs.append(torch.from_numpy(complex_gaussian(3 * N, seed=12345)).cuda())
+        ys.append(torch.zeros_like(xs[-1]))
+
+    def launch(t):
+        j = t % len(blocks)
+        if op == "apply":
+            ctx.apply(kappa, blocks[j], delta, xs[j], ys[j])
+        else:
+            ctx.precond(kappa, blocks[j], delta, xs[j], ys[j])
+
+    for t in range(4 * len(blocks)):
+        launch(t)
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for t in range(iters):
+        launch(t)
+    e.record()
+    torch.cuda.synchronize()
+    del xs, ys
+    return s.elapsed_time(e) / 1e3 / iters
 
 
 def copy_peak(torch, nbytes=2 << 30, iters=20):
@@ -151,40 +172,53 @@ def main():
     ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
     delta = ctx.default_shift()
     kappas, _ = sc_path(args.nk)
+    if args.first > 0:
+        kappas = kappas[:args.first]
     kap_mv = (0.15, 0.05, 0.10)
+    opts = pbr.pbr_opts_default()
+    opts.concurrent = 0 if args.serial_blocks else 1
 
     # ---- matvec roofline (dominant kernel), live HIP-event timing ----
-    mv = matvec_timing(torch, ctx, n, kap_mv, delta, args.mv_iters)
-    mv_full = matvec_timing(torch, ctx, n, kap_mv, delta, max(10, args.mv_iters // 4), blocks=(-1,))
-    t_blk = float(np.mean([mv[b] for b in range(4)]))
+    t_blk = kernel_timing(torch, ctx, n, kap_mv, delta, args.mv_iters, (0, 1, 2, 3), "apply")
+    t_full = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 4), (-1,),
+                           "apply")
+    t_pc = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 2), (0, 1, 2, 3),
+                         "precond")
     nb = n ** 3 // 4
     blk_bytes = BYTES_PER_NODE * nb
     blk_gbs = blk_bytes / t_blk / 1e9
-    full_gbs = BYTES_PER_NODE * n ** 3 / mv_full[-1] / 1e9
+    full_gbs = BYTES_PER_NODE * n ** 3 / t_full / 1e9
+    pc_gbs = PRECOND_BYTES_PER_NODE * nb / t_pc / 1e9
     cpeak = copy_peak(torch)
-    log(f"block matvec {t_blk*1e6:.1f} us = {blk_gbs:.0f} GB/s; full {mv_full[-1]*1e6:.1f} us = "
-        f"{full_gbs:.0f} GB/s; copy peak {cpeak:.0f} GB/s")
+    log(f"block matvec {t_blk*1e6:.1f} us = {blk_gbs:.0f} GB/s; full {t_full*1e6:.1f} us = "
+        f"{full_gbs:.0f} GB/s; block preconditioner {t_pc*1e6:.1f} us; copy {cpeak:.0f} GB/s")
     rec = traffic_record(os.path.join(ROOT, "paper_2606_03599_amd", "csrc", "stencil.hip"),
                          f"matvec_block_n{n}_traffic")
     roof = {"bound": "hbm", "achieved": round(blk_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(blk_gbs / HBM_PEAK_GBS, 4),
             "traffic": (None if rec is None else rec["hbm_bytes_per_launch"]),
-            "kernel": "fused block stencil (A + delta M) x", "algorithmic_bytes": blk_bytes,
-            "avg_launch_us": round(t_blk * 1e6, 2)}
+            "kernel": "apply_stream_kernel: fused block (A + delta M) x",
+            "algorithmic_bytes": blk_bytes, "avg_launch_us": round(t_blk * 1e6, 2)}
+    kernels = {"block_matvec_us": round(t_blk * 1e6, 2), "block_matvec_GBps": round(blk_gbs, 1),
+               "block_matvec_frac_copy": round(blk_gbs / cpeak, 4),
+               "full_matvec_us": round(t_full * 1e6, 2), "full_matvec_GBps": round(full_gbs, 1),
+               "full_matvec_frac_hbm": round(full_gbs / HBM_PEAK_GBS, 4),
+               "block_precond_us": round(t_pc * 1e6, 2),
+               "block_precond_GBps_algorithmic": round(pc_gbs, 1),
+               "copy_peak_GBps": round(cpeak, 1)}
     if args.matvec_only:
-        print(json.dumps({"roofline": roof, "full_matvec_GBps": round(full_gbs, 1),
-                          "copy_peak_GBps": round(cpeak, 1)}))
+        print(json.dumps({"roofline": roof, "kernels": kernels}), flush=True)
         ctx.close()
         return
 
     # ---- the timed steps: blocked band path ----
     for w in range(args.warmup):
         log(f"warmup {w}")
-        ctx.band_path(kappas, args.nev, blocked=True)
+        ctx.band_path(kappas, args.nev, blocked=True, opts=opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ev, st = ctx.band_path(kappas, args.nev, blocked=True)
+        ev, st = ctx.band_path(kappas, args.nev, blocked=True, opts=opts)
         log(f"step {k}: {st.seconds:.2f} s, op_applies {st.op_applies}, pcg avg {st.pcg_avg:.1f}")
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / max(1, args.steps)
@@ -195,42 +229,48 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"two-phase unit cube n={n}^3, {args.nk}-point Gamma-X-M-Gamma-R "
-                               f"path, {args.nev} lowest eigenpairs per k, 4 parity blocks with "
+                               f"path{'' if args.first <= 0 else f' (first {len(kappas)} points)'}, "
+                               f"{args.nev} lowest eigenpairs per k, 4 parity blocks with "
                                "certified merge, shift-invert Lanczos + FFT-preconditioned PCG, "
                                "complex128", "n": n, "nk": args.nk, "nev": args.nev,
-                   "tol": 1e-12, "tol_inner": 1e-12, "radius": 0.35, "seed": 0},
-        "block_matvec_GBps": round(blk_gbs, 1),
-        "block_matvec_frac_hbm": round(blk_gbs / HBM_PEAK_GBS, 4),
-        "full_matvec_GBps": round(full_gbs, 1),
-        "copy_peak_GBps": round(cpeak, 1),
+                   "tol": 1e-12, "tol_inner": 1e-12, "radius": 0.35, "seed": 0,
+                   "block_streams": 1 if args.serial_blocks else 4},
+        "kernels": kernels,
         "pcg_avg": round(st.pcg_avg, 2), "pcg_max": st.pcg_iters_max,
         "op_applies": st.op_applies, "outer_restarts": st.outer_iters,
         "max_rel_resid": st.max_rel_resid,
         "roofline": roof,
     }
-    # ---- full-space comparison (same GPU, same accuracy) ----
-    if not args.no_full:
+    # ---- blocked vs full space on the same GPU, on every full_every-th k-point ----
+    if args.full_every > 0:
+        sub = kappas[::args.full_every]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        evf, stf = ctx.band_path(kappas, args.nev, blocked=False)
+        evb, stb = ctx.band_path(sub, args.nev, blocked=True, opts=opts)
         torch.cuda.synchronize()
-        t_full = time.perf_counter() - t0
-        diff = float(np.max(np.abs(ev - evf) / np.abs(evf)))
-        log(f"full-space path {t_full:.2f} s (blocked {t_step:.2f} s), max rel diff {diff:.2e}")
-        out.update({"full_space_path_s": round(t_full, 3),
-                    "blocked_speedup_vs_full": round(t_full / t_step, 3),
-                    "max_rel_diff_blocked_vs_full": diff,
-                    "full_pcg_avg": round(stf.pcg_avg, 2), "full_op_applies": stf.op_applies})
+        t_b = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        evf, stf = ctx.band_path(sub, args.nev, blocked=False)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        diff = float(np.max(np.abs(evb - evf) / np.abs(evf)))
+        log(f"{len(sub)} k-points: full space {t_f:.2f} s, blocked {t_b:.2f} s, "
+            f"max rel diff {diff:.2e}")
+        out["vs_full_space"] = {
+            "k_points": len(sub), "full_space_s": round(t_f, 3), "blocked_s": round(t_b, 3),
+            "blocked_speedup": round(t_f / t_b, 3), "max_rel_diff_eigenvalues": diff,
+            "full_pcg_avg": round(stf.pcg_avg, 2), "full_op_applies": stf.op_applies,
+            "blocked_op_applies": stb.op_applies}
     ctx.close()
     # ---- CPU oracle baseline (bounded sample, scaled to the path) ----
     if not args.no_cpu:
-        t_mv, t_pc = cpu_sample(n, kap_mv, C21, rho, delta)
+        t_mv_cpu, t_pc_cpu = cpu_sample(n, kap_mv, C21, rho, delta)
         iters = st.pcg_iters_total
-        est = iters * (t_mv + t_pc)
+        est = iters * (t_mv_cpu + t_pc_cpu)
         out["cpu_baseline"] = {
             "value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"one oracle matvec ({t_mv:.2f} s) + one oracle FFT preconditioner "
-                       f"({t_pc:.2f} s) at n={n}, single-threaded; scaled by the {iters} PCG "
+            "sample": (f"one oracle matvec ({t_mv_cpu:.2f} s) + one oracle FFT preconditioner "
+                       f"({t_pc_cpu:.2f} s) at n={n}, single-threaded; scaled by the {iters} PCG "
                        "iterations of the GPU blocked path (the oracle applies a block as the "
                        "full-space operator on a zero-extended vector)")}
     print(json.dumps(out), flush=True)

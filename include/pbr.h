@@ -81,6 +81,10 @@ typedef struct pbr_opts {
   int precond;       /* 1 = FFT-diagonal preconditioner, 0 = none */
   int check_every;   /* PCG iterations between host convergence checks; 0 = automatic */
   int seed;          /* seed of the (deterministic) start vector */
+  int concurrent;    /* pbr_eigs_merged / blocked pbr_band_path: 1 = the four block
+                        solves run at once, one host thread and one HIP stream each
+                        (joined to the context stream before return); 0 = one after
+                        another on the context stream.  Results are identical. */
 } pbr_opts;
 
 /* Statistics of one pbr_solve / pbr_eigs / pbr_eigs_merged / pbr_band_path call. */
@@ -99,7 +103,7 @@ typedef struct pbr_stats {
 } pbr_stats;
 
 /* Fill *o with the defaults: tol 1e-12, tol_inner 1e-12, maxit 300 / 200,
- * ncv automatic, precond 1, check_every automatic, seed 1. */
+ * ncv automatic, precond 1, check_every automatic, seed 1, concurrent 1. */
 void pbr_opts_default(pbr_opts *o);
 
 /* Create a context for an n1 x n2 x n3 grid on HIP device `hip_device`.

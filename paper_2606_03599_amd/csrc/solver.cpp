@@ -538,6 +538,20 @@ void add_stats(pbr_stats* acc, const pbr_stats& one) {
 // the context stream after them on return.
 int solve_blocks(pbr_ctx* c, const double kappa[3], int mask, const int nev_b[4], double shift,
                  const pbr_opts& o, std::vector<double>* vals, pbr_stats* st) {
+  if (!o.concurrent) {
+    int status = ST_OK;
+    for (int b = 0; b < 4; ++b) {
+      if (!(mask & (1 << b))) continue;
+      vals[b].assign(nev_b[b], 0.0);
+      pbr_stats one;
+      std::memset(&one, 0, sizeof(one));
+      const int s = lanczos_eigs(c, kappa, b, nev_b[b], shift, o, vals[b].data(), nullptr, &one);
+      if (s != ST_OK && s != ST_ENOCONV) return s;
+      if (s == ST_ENOCONV) status = ST_ENOCONV;
+      if (st) add_stats(st, one);
+    }
+    return status;
+  }
   PBR_TRY(ensure_block_streams(c));
   for (int b = 0; b < 4; ++b)
     if (mask & (1 << b)) PBR_TRY(ensure_work(c, b));
@@ -615,8 +629,10 @@ int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const 
         }
       }
   }
-  if (st)
+  if (st) {
     for (int b = 0; b < 4; ++b) st->nev_block[b] = nev_b[b];
+    st->n_zero = 4 * nz;  // re-solved blocks are not counted twice
+  }
   return status;
 }
 

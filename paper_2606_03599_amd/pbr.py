@@ -31,7 +31,8 @@ class PbrOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("tol_inner", ctypes.c_double),
                 ("maxit_outer", ctypes.c_int), ("maxit_inner", ctypes.c_int),
                 ("ncv", ctypes.c_int), ("precond", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("seed", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("seed", ctypes.c_int),
+                ("concurrent", ctypes.c_int)]
 
 
 class PbrStats(ctypes.Structure):

@@ -65,14 +65,18 @@ def test_full_eigs_n8(n8, point):
     assert st.n_zero == (12 if point == "gamma" else 0)
 
 
+@pytest.mark.parametrize("concurrent", [1, 0])
 @pytest.mark.parametrize("point", ["k", "gamma"])
-def test_merged_eigs_n8(n8, point):
+def test_merged_eigs_n8(n8, point, concurrent):
     g, ctx, _, _ = n8
     pt = g["points"][point]
-    log(f"eigs_merged n=8 {point}")
-    ev, st = ctx.eigs_merged(pt["kappa"], 12)
+    log(f"eigs_merged n=8 {point} concurrent={concurrent}")
+    o = pbr.pbr_opts_default()
+    o.concurrent = concurrent
+    ev, st = ctx.eigs_merged(pt["kappa"], 12, opts=o)
     ref = np.array(pt["full_lowest"][:12])
     assert np.all(np.abs(ev - ref) <= TOL * np.abs(ref)), (ev, ref)
+    assert st.n_zero == (12 if point == "gamma" else 0)
 
 
 def test_eigenvectors_residual_and_M_normalised(n8):
