@@ -7,15 +7,11 @@
 #include <cmath>
 
 #include "blas.hpp"
+#include "reduce.hpp"
 
 namespace {
 
 constexpr int RT = 256;  // threads per reduction work-group
-
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
 
 // Sum over the work-group; result valid in thread 0.
 __device__ inline double block_sum(double v, double* sh) {

@@ -12,8 +12,32 @@ struct PcgScalars {
   double alpha, beta;
   double bb;     // ||b||^2
   double tol2;   // tol^2
+  double rz_next;  // (r, z) of the current iteration until the p update consumes beta
   int done;      // 0 running, 1 converged, 2 breakdown
   int iters;
+};
+
+// Hooks of the fused PCG iteration into the preconditioner and matvec kernels
+// (with the preconditioner on, one iteration is six launches: matvec with the
+// (p, q) partials; first FFT pass with the alpha, x and r update and the |r|^2
+// partials; second pass, whose first work-group finishes |r|^2 and the
+// convergence test; the mode solve with the (r, z) partials by Parseval; third
+// pass, whose first work-group finishes (r, z) and beta; last pass writing
+// p = z + beta p).  A launch with st == nullptr is the plain preconditioner.
+struct PcgHook {
+  PcgScalars* st = nullptr;
+  int init = 0;                 // first pass of a solve: r = b, x = 0
+  int role = 0;                 // first work-group finishes: 1 |r|^2, 2 (r, z)
+  cplx* x = nullptr;            // solution (first pass)
+  cplx* r = nullptr;            // residual (first pass)
+  const cplx* p = nullptr;      // search direction (first pass)
+  const cplx* q = nullptr;      // (A + shift M) p (first pass)
+  const cplx* b = nullptr;      // right-hand side (first pass, init)
+  const double* red_in = nullptr;  // partials finished by this launch
+  int red_n = 0;
+  double* part_out = nullptr;   // partials written by this launch
+  double tol2 = 0.0;            // init: tol_inner^2
+  double inv_n = 1.0;           // 1 / nodes of the layout (Parseval scale of (r, z))
 };
 
 int blas_part_capacity();

@@ -43,6 +43,8 @@ struct LayoutWork {
   double* part2 = nullptr;
   double* dscal = nullptr;    // small device scalars (256 doubles)
   PcgScalars* st = nullptr;
+  double* ppart = nullptr;    // fused PCG partials: 3 buffers of pcap doubles
+  long pcap = 0;
   double* Wnull = nullptr;    // Gamma null fields (nf x N real, orthonormal after sqrt(rho))
   int nf = 0;
   int block = -2;                // layout of this work area (-1 full, 0..3 blocks)
@@ -100,13 +102,39 @@ int layout_scatter(pbr_ctx* c, int block, const cplx* blk, cplx* full);
 
 // Geometry of a layout at wave vector kappa.
 Geo make_geo(const pbr_ctx* c, int block, const double kappa[3]);
-// y = (A + s M) x in layout `block`; with `skip` (device int) non-null the
-// kernels return at once when *skip != 0 (a converged PCG's remaining iterations)
+// One fused PCG iteration's preconditioner work (see PcgHook): x, r updated
+// with alpha from the (p, q) partials of the matvec (or r = b, x = 0 at init),
+// z the transform buffer, pout = z + beta p (p at init).
+struct PcgStep {
+  PcgScalars* st = nullptr;
+  int init = 0;
+  double tol2 = 0.0;
+  cplx* x = nullptr;
+  cplx* r = nullptr;
+  const cplx* p = nullptr;
+  const cplx* q = nullptr;
+  const cplx* b = nullptr;
+  cplx* z = nullptr;
+  cplx* pout = nullptr;
+  const double* part_pq = nullptr;
+  int n_pq = 0;
+  double* part_rr = nullptr;
+  double* part_rz = nullptr;
+  long part_cap = 0;  // capacity of each partial buffer (doubles)
+};
+
+// y = (A + s M) x in layout `block`.  With `st` non-null the launch does nothing
+// once st->done != 0 and writes per-work-group partials of Re(x^H y) to `part`
+// (their number to *nparts).
 int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
-                 const int* skip = nullptr);
+                 PcgScalars* st = nullptr, double* part = nullptr, long part_cap = 0,
+                 int* nparts = nullptr);
 // z = preconditioner(r) in layout `block`
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
-                   const cplx* r, cplx* z, const int* skip = nullptr);
+                   const cplx* r, cplx* z);
+// the preconditioner passes of one fused PCG iteration (five launches)
+int launch_pcg_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
+                       const PcgStep& P);
 
 // solver drivers (solver.cpp)
 int ensure_work(pbr_ctx* c, int block);

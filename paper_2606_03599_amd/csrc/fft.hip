@@ -30,7 +30,9 @@
 #include <cmath>
 #include <vector>
 
+#include "blas.hpp"
 #include "context.hpp"
+#include "reduce.hpp"
 
 namespace {
 
@@ -133,28 +135,88 @@ struct LineArgs {
   double scale;
   const cplx* in;
   cplx* out;
-  const int* skip;  // optional: the launch does nothing when *skip != 0
+  PcgHook h;         // fused PCG work (h.st == nullptr: plain transform)
 };
+
+// First work-group of a PCG launch: finish the partials of the previous launch.
+__device__ inline void pcg_finish(const PcgHook& H, double* sh) {
+  const double v = block_sum_array(H.red_in, H.red_n, sh);
+  if (threadIdx.x != 0) return;
+  PcgScalars* st = H.st;
+  if (H.role == 1) {  // |r|^2: convergence test
+    if (H.init) {
+      st->bb = v;
+      st->rr = v;
+      st->done = (v == 0.0) ? 1 : 0;
+    } else {
+      st->rr = v;
+      st->iters += 1;
+      if (v <= st->tol2 * st->bb) st->done = 1;
+    }
+  } else if (H.role == 2) {  // (r, z) = (1/N) sum_m c_m^H K(m)^-1 c_m
+    const double rz = v * H.inv_n;
+    st->beta = H.init ? 0.0 : rz / st->rz;
+    st->rz_next = rz;
+  }
+}
 
 // LT: transform length; AXIS: 0 (memory-contiguous lines of length LM) or 1;
 // SPLIT: axis-0 lines of a block, LM = 2 LT, even and odd elements transformed
-// separately.
-template <int LT, int AXIS, int SPLIT, int SIGN>
+// separately.  MODE: 0 plain; 1 first PCG pass (input r after the update
+// r -= alpha q, x += alpha p, or r = b, x = 0 at init; |r|^2 partials);
+// 2 last PCG pass (output p = scale z + beta p instead of z).
+template <int LT, int AXIS, int SPLIT, int SIGN, int MODE>
 __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   constexpr int LM = SPLIT ? 2 * LT : LT;          // line length in memory
   constexpr int B = (FFT_ELEMS / LM) > 0 ? FFT_ELEMS / LM : 1;  // lines per work-group
   __shared__ cplx buf0[B * LM], buf1[B * LM];
-  if (A.skip && __atomic_load_n(A.skip, __ATOMIC_RELAXED)) return;
+  __shared__ double red[FFT_THREADS / 64 + 1];
+  const PcgHook& H = A.h;
+  PcgScalars* st = H.st;
+  const bool first_wg = blockIdx.x == 0 && blockIdx.y == 0;
+  if (st && !(MODE == 1 && H.init) && st->done) return;  // uniform per work-group
+  double alpha = 0.0;
+  if (MODE == 1) {
+    if (H.init) {
+      if (first_wg && threadIdx.x == 0) {
+        st->tol2 = H.tol2;
+        st->iters = 0;
+        st->done = 0;
+        st->alpha = st->beta = st->pq = 0.0;
+      }
+    } else {
+      const double pq = block_sum_array(H.red_in, H.red_n, red);
+      if (!(pq > 0.0)) {  // breakdown: the operator is not positive on p
+        if (first_wg && threadIdx.x == 0) {
+          st->pq = pq;
+          st->done = 2;
+        }
+        return;
+      }
+      alpha = st->rz / pq;
+      if (first_wg && threadIdx.x == 0) {
+        st->pq = pq;
+        st->alpha = alpha;
+      }
+    }
+  } else if (st && H.role && first_wg) {
+    pcg_finish(H, red);
+  }
+  double beta = 0.0;
+  if (MODE == 2) {
+    beta = st->beta;
+    if (first_wg && threadIdx.x == 0) st->rz = st->rz_next;
+  }
   const int comp = blockIdx.y;
   const long l0 = (long)blockIdx.x * B;
   const int nb = (int)min((long)B, A.nlines - l0);
-  const cplx* in = A.in + comp * A.N;
-  cplx* out = A.out + comp * A.N;
+  const long co = comp * A.N;
   const long es = AXIS == 0 ? 1 : A.L1;
   auto base_of = [&](long l) -> long {
     if (AXIS == 0) return l * LM;
     return (l % A.L1) + (l / A.L1) * (long)A.L1 * A.L2;
   };
+  double rr = 0.0;
   for (int w = threadIdx.x; w < B * LM; w += blockDim.x) {
     int b, e;
     if (AXIS == 0) {
@@ -165,12 +227,31 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
       b = w - e * B;
     }
     if (b < nb) {
-      cplx x = in[base_of(l0 + b) + e * es];
+      const long idx = co + base_of(l0 + b) + e * es;
+      cplx x;
+      if (MODE == 1) {
+        if (H.init) {
+          x = H.b[idx];
+          H.r[idx] = x;
+          H.x[idx] = mk(0, 0);
+        } else {
+          H.x[idx] = cfma(alpha, H.p[idx], H.x[idx]);
+          x = cfma(-alpha, H.q[idx], H.r[idx]);
+          H.r[idx] = x;
+        }
+        rr = fma(x.x, x.x, fma(x.y, x.y, rr));
+      } else {
+        x = A.in[idx];
+      }
       const int slot = SPLIT ? 2 * b + (e & 1) : b;
       const int y = SPLIT ? e >> 1 : e;
       if (SIGN < 0) x = cmul(x, A.twist[y]);
       buf0[slot * LT + y] = x;
     }
+  }
+  if (MODE == 1) {
+    const double s = block_sum_all(rr, red);
+    if (threadIdx.x == 0) H.part_out[comp * gridDim.x + blockIdx.x] = s;
   }
   __syncthreads();
   const cplx* res = fft_stages<LT, 0, 1, SIGN>(A.roots, buf0, buf1, SPLIT ? 2 * nb : nb);
@@ -188,7 +269,11 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
       const int y = SPLIT ? e >> 1 : e;
       cplx x = res[slot * LT + y];
       if (SIGN > 0) x = cmul(x, cconj(A.twist[y]));
-      out[base_of(l0 + b) + e * es] = cscale(A.scale, x);
+      const long idx = co + base_of(l0 + b) + e * es;
+      if (MODE == 2 && !H.init)
+        A.out[idx] = cfma(beta, A.out[idx], cscale(A.scale, x));
+      else
+        A.out[idx] = cscale(A.scale, x);
     }
   }
 }
@@ -210,7 +295,8 @@ struct SolveArgs {
   double Cref[21];
   double shift_rho;
   cplx* data;
-  const int* skip;  // optional: the launch does nothing when *skip != 0
+  PcgScalars* st;     // fused PCG: skip once converged, write (r, z) partials
+  double* part_out;
 };
 
 // K(m)^-1 b for the mode whose one-step phases are Ea = e^{i alpha},
@@ -290,7 +376,8 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   constexpr int BI = solve_bi(L3T, BLK);
   constexpr int NL = 3 * BI;  // lines of one work-group: component-major
   __shared__ cplx buf0[NL * L3T], buf1[NL * L3T];
-  if (S.skip && __atomic_load_n(S.skip, __ATOMIC_RELAXED)) return;
+  __shared__ double red[FFT_THREADS / 64 + 1];
+  if (S.st && S.st->done) return;
   const int groups_i = (S.L1 + BI - 1) / BI;
   const int q = blockIdx.x / groups_i;
   const int i0 = (blockIdx.x % groups_i) * BI;
@@ -309,6 +396,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   cplx* f = fft_stages<L3T, 0, 1, -1>(S.roots, buf0, buf1, NL);
   cplx* g = (f == buf0) ? buf1 : buf0;
   const cplx Eb = S.e2[q];
+  double rz = 0.0;  // sum over this work-group's modes of Re(c^H K^-1 c)
   if (!BLK) {
     for (int w = threadIdx.x; w < bi * L3T; w += blockDim.x) {
       const int di = w / L3T, r = w - di * L3T;
@@ -317,7 +405,10 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       for (int a = 0; a < 3; ++a) bv[a] = f[(a * BI + di) * L3T + r];
       mode_solve(S, S.e1[i0 + di], Eb, S.e3[r], bv, xv);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) g[(a * BI + di) * L3T + r] = xv[a];
+      for (int a = 0; a < 3; ++a) {
+        g[(a * BI + di) * L3T + r] = xv[a];
+        rz = fma(bv[a].x, xv[a].x, fma(bv[a].y, xv[a].y, rz));
+      }
     }
   } else {
     // sub-lattice p has offsets o2(p) = (a+p)&1, o3(p) = (a+c+p)&1
@@ -344,10 +435,16 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       mode_solve(S, mk(-Ea.x, -Ea.y), Eb, Eg, c1, z1);  // m1 = m1' + n1/2: alpha + pi
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
+        rz = fma(c0[a].x, z0[a].x, fma(c0[a].y, z0[a].y, rz));
+        rz = fma(c1[a].x, z1[a].x, fma(c1[a].y, z1[a].y, rz));
         g[(a * BI + 2 * dp) * L3T + r] = cmulc(T0, cadd(z0[a], z1[a]));
         g[(a * BI + 2 * dp + 1) * L3T + r] = cmulc(t1e, csub(z0[a], z1[a]));
       }
     }
+  }
+  if (S.part_out) {
+    const double v = block_sum_all(rz, red);
+    if (threadIdx.x == 0) S.part_out[blockIdx.x] = v;
   }
   __syncthreads();
   const cplx* res = fft_stages<L3T, 0, 1, +1>(S.roots, g, f, NL);
@@ -414,12 +511,12 @@ int ensure_tables(pbr_ctx* c, int block, const double kappa[3]) {
 typedef void (*LineKernel)(LineArgs);
 typedef void (*SolveKernel)(SolveArgs);
 
-template <int AXIS, int SPLIT, int SIGN>
+template <int AXIS, int SPLIT, int SIGN, int MODE>
 LineKernel line_kernel(int L) {
   switch (L) {
 #define PBR_CASE(n) \
   case n:           \
-    return fft_lines_kernel<n, AXIS, SPLIT, SIGN>;
+    return fft_lines_kernel<n, AXIS, SPLIT, SIGN, MODE>;
     PBR_FFT_LENGTHS(PBR_CASE)
 #undef PBR_CASE
     default:
@@ -440,8 +537,10 @@ SolveKernel solve_kernel(int L) {
   }
 }
 
-int run_lines(pbr_ctx* c, int block, int axis, int sign, const cplx* in, cplx* out,
-              double scale, const int* skip) {
+// One pass of lines along `axis`; mode 1 / 2 are the first / last PCG pass.
+// *nparts receives the number of partials a mode-1 launch writes.
+int run_lines(pbr_ctx* c, int block, int axis, int sign, int mode, const cplx* in, cplx* out,
+              double scale, const PcgHook& h, long part_cap, int* nparts) {
   FftTables& T = c->fft[block + 1];
   const long N = c->layout_nodes(block);
   LineArgs A;
@@ -458,26 +557,39 @@ int run_lines(pbr_ctx* c, int block, int axis, int sign, const cplx* in, cplx* o
   A.scale = scale;
   A.in = in;
   A.out = out;
-  A.skip = skip;
+  A.h = h;
   LineKernel k = nullptr;
-  if (axis == 0 && split)
-    k = sign < 0 ? line_kernel<0, 1, -1>(LT) : line_kernel<0, 1, 1>(LT);
-  else if (axis == 0)
-    k = sign < 0 ? line_kernel<0, 0, -1>(LT) : line_kernel<0, 0, 1>(LT);
-  else
-    k = sign < 0 ? line_kernel<1, 0, -1>(LT) : line_kernel<1, 0, 1>(LT);
+  if (axis == 0 && split) {
+    if (sign < 0)
+      k = mode == 1 ? line_kernel<0, 1, -1, 1>(LT) : line_kernel<0, 1, -1, 0>(LT);
+    else
+      k = mode == 2 ? line_kernel<0, 1, 1, 2>(LT) : line_kernel<0, 1, 1, 0>(LT);
+  } else if (axis == 0) {
+    if (sign < 0)
+      k = mode == 1 ? line_kernel<0, 0, -1, 1>(LT) : line_kernel<0, 0, -1, 0>(LT);
+    else
+      k = mode == 2 ? line_kernel<0, 0, 1, 2>(LT) : line_kernel<0, 0, 1, 0>(LT);
+  } else {
+    k = sign < 0 ? line_kernel<1, 0, -1, 0>(LT) : line_kernel<1, 0, 1, 0>(LT);
+  }
   if (!k) {
     c->set_error("FFT lengths must be 2^a 3^b up to 256 (blocks: 512 along i)");
     return ST_EINVAL;
   }
   const int B = std::max(1, FFT_ELEMS / LM);
   dim3 grid(ceil_div(A.nlines, B), 3);
+  if (nparts) *nparts = (int)(grid.x * 3);
+  if (mode == 1 && (long)grid.x * 3 > part_cap) {
+    c->set_error("grid too large for the PCG partial buffers");
+    return ST_EINVAL;
+  }
   hipLaunchKernelGGL(k, grid, dim3(FFT_THREADS), 0, c->stream_of(block), A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
 
-int run_solve(pbr_ctx* c, int block, double shift, cplx* z, const int* skip) {
+int run_solve(pbr_ctx* c, int block, double shift, cplx* z, PcgScalars* st, double* part_out,
+              long part_cap, int* nparts) {
   FftTables& T = c->fft[block + 1];
   SolveArgs S;
   S.L1 = c->n1;
@@ -496,7 +608,8 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z, const int* skip) {
   for (int qq = 0; qq < 21; ++qq) S.Cref[qq] = c->Cref[qq];
   S.shift_rho = shift * c->rho_ref;
   S.data = z;
-  S.skip = skip;
+  S.st = st;
+  S.part_out = part_out;
   const SolveKernel k = block >= 0 ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
   if (!k) {
     c->set_error("FFT lengths must be 2^a 3^b up to 256");
@@ -504,8 +617,13 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z, const int* skip) {
   }
   const int bi = solve_bi(S.L3, block >= 0 ? 1 : 0);
   const int groups_i = (S.L1 + bi - 1) / bi;
-  hipLaunchKernelGGL(k, dim3((unsigned)(groups_i * S.L2)), dim3(FFT_THREADS), 0,
-                     c->stream_of(block), S);
+  const long nwg = (long)groups_i * S.L2;
+  if (nparts) *nparts = (int)nwg;
+  if (part_out && nwg > part_cap) {
+    c->set_error("grid too large for the PCG partial buffers");
+    return ST_EINVAL;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)nwg), dim3(FFT_THREADS), 0, c->stream_of(block), S);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
@@ -513,13 +631,54 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z, const int* skip) {
 }  // namespace
 
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, const cplx* r,
-                   cplx* z, const int* skip) {
+                   cplx* z) {
   PBR_TRY(ensure_tables(c, block, kappa));
   const long N = c->layout_nodes(block);
-  PBR_TRY(run_lines(c, block, 0, -1, r, z, 1.0, skip));
-  PBR_TRY(run_lines(c, block, 1, -1, z, z, 1.0, skip));
-  PBR_TRY(run_solve(c, block, shift, z, skip));
-  PBR_TRY(run_lines(c, block, 1, +1, z, z, 1.0, skip));
-  PBR_TRY(run_lines(c, block, 0, +1, z, z, 1.0 / (double)N, skip));
+  const PcgHook none;
+  PBR_TRY(run_lines(c, block, 0, -1, 0, r, z, 1.0, none, 0, nullptr));
+  PBR_TRY(run_lines(c, block, 1, -1, 0, z, z, 1.0, none, 0, nullptr));
+  PBR_TRY(run_solve(c, block, shift, z, nullptr, nullptr, 0, nullptr));
+  PBR_TRY(run_lines(c, block, 1, +1, 0, z, z, 1.0, none, 0, nullptr));
+  PBR_TRY(run_lines(c, block, 0, +1, 0, z, z, 1.0 / (double)N, none, 0, nullptr));
+  return ST_OK;
+}
+
+int launch_pcg_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
+                       const PcgStep& P) {
+  PBR_TRY(ensure_tables(c, block, kappa));
+  const long N = c->layout_nodes(block);
+  PcgHook h;
+  h.st = P.st;
+  h.init = P.init;
+  h.tol2 = P.tol2;
+  h.inv_n = 1.0 / (double)N;
+  int n_rr = 0, n_rz = 0;
+  // pass 1: update (or initialise) x and r, |r|^2 partials, forward lines of r
+  PcgHook h1 = h;
+  h1.x = P.x;
+  h1.r = P.r;
+  h1.p = P.p;
+  h1.q = P.q;
+  h1.b = P.b;
+  h1.red_in = P.part_pq;
+  h1.red_n = P.n_pq;
+  h1.part_out = P.part_rr;
+  PBR_TRY(run_lines(c, block, 0, -1, 1, nullptr, P.z, 1.0, h1, P.part_cap, &n_rr));
+  // pass 2: first work-group finishes |r|^2 and the convergence test
+  PcgHook h2 = h;
+  h2.role = 1;
+  h2.red_in = P.part_rr;
+  h2.red_n = n_rr;
+  PBR_TRY(run_lines(c, block, 1, -1, 0, P.z, P.z, 1.0, h2, P.part_cap, nullptr));
+  // pass 3: mode solve with (r, z) partials
+  PBR_TRY(run_solve(c, block, shift, P.z, P.st, P.part_rz, P.part_cap, &n_rz));
+  // pass 4: first work-group finishes (r, z) and beta
+  PcgHook h4 = h;
+  h4.role = 2;
+  h4.red_in = P.part_rz;
+  h4.red_n = n_rz;
+  PBR_TRY(run_lines(c, block, 1, +1, 0, P.z, P.z, 1.0, h4, P.part_cap, nullptr));
+  // pass 5: p = z + beta p
+  PBR_TRY(run_lines(c, block, 0, +1, 2, P.z, P.pout, 1.0 / (double)N, h, P.part_cap, nullptr));
   return ST_OK;
 }

@@ -199,6 +199,8 @@ int ensure_work(pbr_ctx* c, int block) {
   PBR_TRY(dev_alloc(c, (void**)&W.part2, sizeof(double) * 1024 * 2));
   PBR_TRY(dev_alloc(c, (void**)&W.dscal, sizeof(double) * 4096));
   PBR_TRY(dev_alloc(c, (void**)&W.st, sizeof(PcgScalars)));
+  W.pcap = N / 128 + 4096;
+  PBR_TRY(dev_alloc(c, (void**)&W.ppart, sizeof(double) * 3 * W.pcap));
   if (!W.hpin) PBR_HIP(c, hipHostMalloc((void**)&W.hpin, sizeof(double) * 32768));
   return ST_OK;
 }
@@ -210,42 +212,68 @@ int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const 
   const hipStream_t SO = c->stream_of(block);
   const long n3 = 3 * W.N;
   const Geo g = make_geo(c, block, kappa);
-  PBR_TRY(vec_zero(c, SO, n3, x));
-  PBR_TRY(vec_copy(c, SO, n3, b, W.r));
-  if (o.precond)
-    PBR_TRY(launch_precond(c, kappa, block, shift, W.r, W.z));
-  else
-    PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
-  PBR_TRY(vec_copy(c, SO, n3, W.z, W.p));
-  PBR_TRY(pcg_init_async(c, SO, n3, W.r, W.z, o.tol_inner, W.part, W.part2, W.st));
-  const int chunk_auto = 10;
-  const int chunk = o.check_every > 0 ? o.check_every : chunk_auto;
+  const int chunk = o.check_every > 0 ? o.check_every : 10;
   int done_iters = 0;
   PcgScalars hs;
-  for (;;) {
-    const int todo = std::min(chunk, o.maxit_inner - done_iters);
-    if (todo <= 0) break;
-    const int* skip = &W.st->done;  // later launches of a converged chunk are no-ops
-    for (int it = 0; it < todo; ++it) {
-      PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q, skip));
-      PBR_TRY(pcg_alpha(c, SO, n3, W.p, W.q, W.part, W.st));
-      PBR_TRY(pcg_xr(c, SO, n3, x, W.r, W.p, W.q, W.part, W.st));
-      if (o.precond)
-        PBR_TRY(launch_precond(c, kappa, block, shift, W.r, W.z, skip));
-      else
-        PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
-      PBR_TRY(pcg_beta_p(c, SO, n3, W.r, W.z, W.p, W.part, W.st));
-    }
+  auto read_state = [&]() -> int {
     PBR_HIP(c, hipMemcpyAsync(W.hpin, W.st, sizeof(PcgScalars), hipMemcpyDeviceToHost, SO));
     PBR_HIP(c, hipStreamSynchronize(SO));
     std::memcpy(&hs, W.hpin, sizeof(PcgScalars));
-    done_iters = hs.iters;
-    if (hs.done) break;
+    return ST_OK;
+  };
+  if (o.precond) {
+    // fused iteration: matvec (+ (p, q) partials) and five preconditioner passes
+    // that also update x, r and p and finish the CG scalars on the device
+    PcgStep P;
+    P.st = W.st;
+    P.tol2 = o.tol_inner * o.tol_inner;
+    P.x = x;
+    P.r = W.r;
+    P.p = W.p;
+    P.q = W.q;
+    P.b = b;
+    P.z = W.z;
+    P.pout = W.p;
+    P.part_pq = W.ppart;
+    P.part_rr = W.ppart + W.pcap;
+    P.part_rz = W.ppart + 2 * W.pcap;
+    P.part_cap = W.pcap;
+    P.init = 1;
+    PBR_TRY(launch_pcg_precond(c, kappa, block, shift, P));
+    P.init = 0;
+    for (;;) {
+      const int todo = std::min(chunk, o.maxit_inner - done_iters);
+      if (todo <= 0) break;
+      for (int it = 0; it < todo; ++it) {
+        PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q, W.st, W.ppart, W.pcap, &P.n_pq));
+        PBR_TRY(launch_pcg_precond(c, kappa, block, shift, P));
+      }
+      PBR_TRY(read_state());
+      done_iters = hs.iters;
+      if (hs.done) break;
+    }
+  } else {
+    PBR_TRY(vec_zero(c, SO, n3, x));
+    PBR_TRY(vec_copy(c, SO, n3, b, W.r));
+    PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
+    PBR_TRY(vec_copy(c, SO, n3, W.z, W.p));
+    PBR_TRY(pcg_init_async(c, SO, n3, W.r, W.z, o.tol_inner, W.part, W.part2, W.st));
+    for (;;) {
+      const int todo = std::min(chunk, o.maxit_inner - done_iters);
+      if (todo <= 0) break;
+      for (int it = 0; it < todo; ++it) {
+        PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q, W.st));
+        PBR_TRY(pcg_alpha(c, SO, n3, W.p, W.q, W.part, W.st));
+        PBR_TRY(pcg_xr(c, SO, n3, x, W.r, W.p, W.q, W.part, W.st));
+        PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
+        PBR_TRY(pcg_beta_p(c, SO, n3, W.r, W.z, W.p, W.part, W.st));
+      }
+      PBR_TRY(read_state());
+      done_iters = hs.iters;
+      if (hs.done) break;
+    }
   }
-  // final state
-  PBR_HIP(c, hipMemcpyAsync(W.hpin, W.st, sizeof(PcgScalars), hipMemcpyDeviceToHost, SO));
-  PBR_HIP(c, hipStreamSynchronize(SO));
-  std::memcpy(&hs, W.hpin, sizeof(PcgScalars));
+  PBR_TRY(read_state());
   *iters = hs.iters;
   *conv = (hs.done == 1) ? 1 : 0;
   if (hs.done == 2) {

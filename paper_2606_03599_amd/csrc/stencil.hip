@@ -33,7 +33,9 @@
 //    ring re-reads of C and x in that XCD's L2;
 //  * all global accesses are buffer loads/stores with 32-bit offsets (one
 //    descriptor per array, scalar plane offsets).
+#include "blas.hpp"
 #include "context.hpp"
+#include "reduce.hpp"
 
 namespace {
 
@@ -46,7 +48,8 @@ struct ApplyArgs {
   cplx* y;
   const double* C;
   const double* rho;
-  const int* skip;    // optional: the launch does nothing when *skip != 0
+  const PcgScalars* st;  // optional: the launch does nothing once st->done != 0
+  double* part;           // optional: per-work-group partials of Re(x^H y)
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -192,7 +195,8 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   static_assert(NH <= 64, "tau ring must fit in one wave");
   __shared__ cplx tau_s[6 * NP];
   __shared__ cplx x_s[3][3 * NX];
-  if (A.skip && __atomic_load_n(A.skip, __ATOMIC_RELAXED)) return;  // whole work-group
+  __shared__ double red[NT / 64 + 1];
+  if (A.st && A.st->done) return;  // whole work-group
   const Geo& g = A.g;
   const int L1 = g.L1, L2 = g.L2, L3 = g.L3;
   const int N = A.N;
@@ -316,6 +320,7 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   for (int a = 0; a < 3; ++a) A0[a] = A1[a] = A2[a] = mk(0, 0);
   cplx xprev[3];
   double rprev = 0.0;
+  double xy = 0.0;  // Re(x^H y) over this lane's outputs
 
   // ---- prologue: velocity planes k0-2 .. k0, stiffness of tau plane k0-1 ----
   {
@@ -406,7 +411,11 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
         const int o = io + L1 * (jo + L2 * t);
         const double sr = A.s * rprev;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) stc(ry, cfma(sr, xprev[a], A0[a]), o * 16, a * cs);
+        for (int a = 0; a < 3; ++a) {
+          const cplx yv = cfma(sr, xprev[a], A0[a]);
+          stc(ry, yv, o * 16, a * cs);
+          xy = fma(xprev[a].x, yv.x, fma(xprev[a].y, yv.y, xy));
+        }
       }
     }
     // velocity plane s+2 replaces plane s-1 in the window
@@ -424,6 +433,10 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
     need_cur = need_nxt;
     __syncthreads();
   }
+  if (A.part) {
+    const double v = block_sum_all(xy, red);
+    if (tid == 0) A.part[blockIdx.x] = v;
+  }
 }
 
 constexpr int TILE_I = 16, TILE_J = 16;
@@ -431,7 +444,7 @@ constexpr int TILE_I = 16, TILE_J = 16;
 }  // namespace
 
 int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
-                 const int* skip) {
+                 PcgScalars* st, double* part, long part_cap, int* nparts) {
   DevMaterial& M = c->material(block);
   if (M.N * 168L >= (1L << 31)) {
     c->set_error("grid too large for 32-bit buffer offsets of the stencil kernel");
@@ -445,7 +458,8 @@ int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, c
   A.y = y;
   A.C = M.C;
   A.rho = M.rho;
-  A.skip = skip;
+  A.st = st;
+  A.part = part;
   A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
   A.tiles_j = (g.L2 + TILE_J - 1) / TILE_J;
   // chunk length: about one work-group per CU (256 CUs); longer chunks amortise
@@ -457,6 +471,11 @@ int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, c
   A.chunk = chunk;
   const int nchunks = (g.L3 + chunk - 1) / chunk;
   const unsigned grid = (unsigned)(tiles * nchunks);
+  if (nparts) *nparts = (int)grid;
+  if (part && (long)grid > part_cap) {
+    c->set_error("grid too large for the PCG partial buffers");
+    return ST_EINVAL;
+  }
   hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
                      dim3(TILE_I * TILE_J + 64), 0, c->stream_of(block), A);
   PBR_HIP(c, hipGetLastError());
