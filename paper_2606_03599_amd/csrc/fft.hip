@@ -320,33 +320,34 @@ __device__ inline void mode_solve(const SolveArgs& S, cplx Ea, cplx Eb, cplx Eg,
     for (int d = 0; d <= 4; ++d) acc = cfma(S.cf[m][d], sd[d], acc);
     e[m] = acc;
   }
-  const cplx z = mk(0, 0);
-  const cplx P[3][6] = {{e[0], z, z, z, e[2], e[1]},
-                        {z, e[1], z, e[2], z, e[0]},
-                        {z, z, e[2], e[1], e[0], z}};
-  cplx W[3][6];
+  // K = Bhat C Bhat^H with Bhat's rows (Voigt columns, symbol) sparse:
+  //   u1: (11, e1) (13, e3) (12, e2);  u2: (22, e2) (23, e3) (12, e1);
+  //   u3: (33, e3) (23, e2) (13, e1)
+  // so K[r][c] = sum over the 3 x 3 pairs of C[k][l] e_a conj(e_b).
+  constexpr int VK[3][3] = {{0, 4, 5}, {1, 3, 5}, {2, 3, 4}};  // Voigt columns of row r
+  constexpr int VE[3][3] = {{0, 2, 1}, {1, 2, 0}, {2, 1, 0}};  // symbol index of each
+  cplx G[3][3];  // G[a][b] = e_a conj(e_b)
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int col = 0; col < 6; ++col) {
-      cplx acc = mk(0, 0);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int rr = k <= col ? k : col, cc = k <= col ? col : k;
-        const double cv = S.Cref[rr * 6 - (rr * (rr - 1)) / 2 + (cc - rr)];
-        acc = cfma(cv, P[r][k], acc);
-      }
-      W[r][col] = acc;
-    }
+    for (int b2 = 0; b2 < 3; ++b2) G[a][b2] = cmulc(e[b2], e[a]);
   cplx K[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int col = 0; col < 3; ++col) {
+    for (int col = r; col < 3; ++col) {
       cplx acc = mk(0, 0);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) acc = cmad(W[r][k], cconj(P[col][k]), acc);
+      for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          const int k = VK[r][u], l = VK[col][v];
+          const int rr = k <= l ? k : l, cc = k <= l ? l : k;
+          const double cv = S.Cref[rr * 6 - (rr * (rr - 1)) / 2 + (cc - rr)];
+          acc = cfma(cv, G[VE[r][u]][VE[col][v]], acc);
+        }
       K[r][col] = acc;
+      K[col][r] = cconj(acc);
     }
 #pragma unroll
   for (int r = 0; r < 3; ++r) K[r][r].x += S.shift_rho;
@@ -366,8 +367,11 @@ __device__ inline void mode_solve(const SolveArgs& S, cplx Ea, cplx Eb, cplx Eg,
   x[0] = cscale(1.0 / l00, csub(csub(y0, cmulc(l10, x[1])), cmulc(l20, x[2])));
 }
 
+// i-values per work-group of the solve pass: 1536 complex per LDS buffer gives
+// 8 consecutive i (128-byte segments) for a 64-long third axis.
+constexpr int SOLVE_ELEMS = 1536;
 constexpr int solve_bi(int L3, int blocked) {
-  const int b = FFT_ELEMS / (3 * L3);
+  const int b = SOLVE_ELEMS / (3 * L3);
   return blocked ? (b >= 2 ? (b & ~1) : 2) : (b >= 1 ? b : 1);
 }
 

@@ -347,17 +347,46 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
   PBR_TRY(st_err);
   PBR_TRY(vec_scale(c, SO, n3, W.U, 1.0 / nrm));
 
-  std::vector<zc> H((size_t)m * m, zc(0, 0));  // column-major
+  std::vector<zc> H((size_t)m * m, zc(0, 0));  // column-major, leading dimension ldh
+  const int ldh = m;
   std::vector<double> beta(m, 0.0);
   std::vector<double> theta(m);
   std::vector<double> Yr(2 * (size_t)m * m);
+  std::vector<double> Hd(2 * (size_t)m * m);
   std::vector<double> hbuf(4 * m + 8);
   int j0 = 0;
   int restarts = 0;
   int nconv = 0;
   bool exhausted = false;
   std::vector<int> order;
+  // Rayleigh-Ritz on the leading mm x mm block of H; the Ritz residuals of the
+  // Krylov-Schur relation are |b_last * (last entry of the Ritz vector)|.
+  auto ritz = [&](int mm, double bl) -> int {
+    for (int jj = 0; jj < mm; ++jj)
+      for (int ii = 0; ii < mm; ++ii) {
+        Hd[2 * ((size_t)jj * mm + ii)] = H[(size_t)jj * ldh + ii].real();
+        Hd[2 * ((size_t)jj * mm + ii) + 1] = H[(size_t)jj * ldh + ii].imag();
+      }
+    if (pbr_host_heev(mm, Hd.data(), theta.data(), Yr.data()) != 0) {
+      c->set_error("Rayleigh-Ritz eigensolver failed");
+      return ST_EINVAL;
+    }
+    order.resize(mm);
+    for (int i = 0; i < mm; ++i) order[i] = mm - 1 - i;  // largest mu first
+    nconv = 0;
+    for (int i = 0; i < std::min(nev, mm); ++i) {
+      const int col = order[i];
+      const zc ylast(Yr[2 * ((size_t)col * mm + (mm - 1))],
+                     Yr[2 * ((size_t)col * mm + (mm - 1)) + 1]);
+      if (bl * std::abs(ylast) <= o.tol * std::abs(theta[col]))
+        ++nconv;
+      else
+        break;
+    }
+    return ST_OK;
+  };
   for (;;) {
+    bool early = false;
     for (int j = j0; j < m; ++j) {
       cplx* uj = W.U + (long)j * ld;
       PBR_TRY(op_apply(c, block, kappa, shift, o, uj, W.w, cnt));
@@ -379,14 +408,14 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
       const double b = vnorm(c, W, W.w, &st_err);
       PBR_TRY(st_err);
       for (int i = 0; i <= j; ++i) {
-        H[(size_t)j * m + i] = h[i];
-        H[(size_t)i * m + j] = std::conj(h[i]);
+        H[(size_t)j * ldh + i] = h[i];
+        H[(size_t)i * ldh + j] = std::conj(h[i]);
       }
-      H[(size_t)j * m + j] = zc(h[j].real(), 0.0);
+      H[(size_t)j * ldh + j] = zc(h[j].real(), 0.0);
       beta[j] = b;
       if (j + 1 < m) {
-        H[(size_t)j * m + (j + 1)] = b;
-        H[(size_t)(j + 1) * m + j] = b;
+        H[(size_t)j * ldh + (j + 1)] = b;
+        H[(size_t)(j + 1) * ldh + j] = b;
       }
       cplx* un = W.U + (long)(j + 1) * ld;
       if (b > 1e-14 * std::abs(h[j]) && b > 0.0) {
@@ -396,46 +425,25 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
         // invariant subspace: the Ritz values of H are exact
         beta[j] = 0.0;
         if (j + 1 < m) {
-          H[(size_t)j * m + (j + 1)] = 0.0;
-          H[(size_t)(j + 1) * m + j] = 0.0;
+          H[(size_t)j * ldh + (j + 1)] = 0.0;
+          H[(size_t)(j + 1) * ldh + j] = 0.0;
         }
         m = j + 1;
         exhausted = true;
         break;
       }
-    }
-    // Rayleigh-Ritz on the m x m projected matrix
-    std::vector<double> Hd(2 * (size_t)m * m);
-    {
-      // H may have been allocated with a larger leading dimension before an
-      // early exit shrank m; rebuild a compact copy.
-      const int ldh = (int)std::sqrt((double)H.size());
-      for (int jj = 0; jj < m; ++jj)
-        for (int ii = 0; ii < m; ++ii) {
-          Hd[2 * ((size_t)jj * m + ii)] = H[(size_t)jj * ldh + ii].real();
-          Hd[2 * ((size_t)jj * m + ii) + 1] = H[(size_t)jj * ldh + ii].imag();
+      // convergence test after every step once the basis exceeds nev: stop
+      // as soon as the wanted Ritz pairs have converged
+      if (j + 1 > nev && j + 1 < m) {
+        PBR_TRY(ritz(j + 1, beta[j]));
+        if (nconv >= nev) {
+          m = j + 1;
+          early = true;
+          break;
         }
+      }
     }
-    Yr.assign(2 * (size_t)m * m, 0.0);
-    theta.assign(m, 0.0);
-    if (pbr_host_heev(m, Hd.data(), theta.data(), Yr.data()) != 0) {
-      c->set_error("Rayleigh-Ritz eigensolver failed");
-      return ST_EINVAL;
-    }
-    // largest mu first
-    order.resize(m);
-    for (int i = 0; i < m; ++i) order[i] = m - 1 - i;
-    const double bl = beta[m - 1];
-    nconv = 0;
-    for (int i = 0; i < std::min(nev, m); ++i) {
-      const int col = order[i];
-      const zc ylast(Yr[2 * ((size_t)col * m + (m - 1))], Yr[2 * ((size_t)col * m + (m - 1)) + 1]);
-      const double res = bl * std::abs(ylast);
-      if (res <= o.tol * std::abs(theta[col]))
-        ++nconv;
-      else
-        break;
-    }
+    if (!early) PBR_TRY(ritz(m, beta[m - 1]));
     if (nconv >= nev || exhausted || restarts >= o.maxit_outer) break;
     // thick restart: keep kk Ritz vectors
     int kk = nev + (m - nev) / 2;
@@ -451,7 +459,7 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
     PBR_TRY(vec_copy(c, SO, n3, W.U + (long)m * ld, W.U2 + (long)kk * ld));
     std::swap(W.U, W.U2);
     std::fill(H.begin(), H.end(), zc(0, 0));
-    for (int i = 0; i < kk; ++i) H[(size_t)i * m + i] = theta[order[i]];
+    for (int i = 0; i < kk; ++i) H[(size_t)i * ldh + i] = theta[order[i]];
     j0 = kk;
     ++restarts;
   }
