@@ -195,7 +195,7 @@ pbr_status pbr_create(pbr_ctx** out, int n1, int n2, int n3, const double* A_lat
       c->own_stream = (e == hipSuccess);
     }
   }
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->hpinned, sizeof(double) * 4 * 8192);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->hpinned, sizeof(double) * PBR_PINNED);
   if (e != hipSuccess) {
     g_create_error = std::string("HIP device setup failed: ") + hipGetErrorString(e);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -228,19 +228,10 @@ void pbr_destroy(pbr_ctx* c) {
     dev_free(W.part);
     dev_free(W.part2);
     dev_free(W.dscal);
-    dev_free(W.st);
+    dev_free(W.ppart);
     dev_free(W.Wnull);
   }
-  for (auto& W : c->work)
-    if (W.hpin) (void)hipHostFree(W.hpin);
-  for (int b = 0; b < 4; ++b) {
-    if (c->bstream[b]) {
-      (void)hipStreamSynchronize(c->bstream[b]);
-      (void)hipStreamDestroy(c->bstream[b]);
-    }
-    if (c->join_ev[b]) (void)hipEventDestroy(c->join_ev[b]);
-  }
-  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  dev_free(c->st_all);
   if (c->hpinned) (void)hipHostFree(c->hpinned);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;

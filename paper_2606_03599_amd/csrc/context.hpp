@@ -11,6 +11,11 @@
 #include "common.hpp"
 #include "geometry.hpp"
 
+// Layouts batched into one launch at most: the four parity blocks.
+#define PBR_MAX_BATCH 4
+// Doubles of pinned host scratch per context.
+#define PBR_PINNED 32768
+
 // Device material in one layout: C as 21 planes of N doubles (SoA), rho, sqrt(rho).
 struct DevMaterial {
   long N = 0;
@@ -47,9 +52,7 @@ struct LayoutWork {
   long pcap = 0;
   double* Wnull = nullptr;    // Gamma null fields (nf x N real, orthonormal after sqrt(rho))
   int nf = 0;
-  int block = -2;                // layout of this work area (-1 full, 0..3 blocks)
-  hipStream_t stream = nullptr;  // stream of this layout's work (null: the context stream)
-  double* hpin = nullptr;        // pinned host scratch of this layout (32768 doubles)
+  int block = -2;             // layout of this work area (-1 full, 0..3 blocks)
 };
 
 struct pbr_ctx {
@@ -72,12 +75,8 @@ struct pbr_ctx {
   FftTables fft[5];
   LayoutWork work[5];
 
-  double* hpinned = nullptr;      // pinned host scratch (4096 doubles)
-  // Streams of the four concurrent block solves (created on first use, default
-  // priority) and the events that fork them from / join them to `stream`.
-  hipStream_t bstream[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* hpinned = nullptr;      // pinned host scratch (PBR_PINNED doubles)
+  PcgScalars* st_all = nullptr;   // device CG scalars of the 5 layouts, contiguous
 
   std::string err;
   std::mutex err_mu;
@@ -87,9 +86,6 @@ struct pbr_ctx {
   }
 
   DevMaterial& material(int block) { return mat[block + 1]; }
-  hipStream_t stream_of(int block) const {
-    return work[block + 1].stream ? work[block + 1].stream : stream;
-  }
   long layout_nodes(int block) const { return block < 0 ? n : n / 4; }
 };
 
@@ -106,6 +102,7 @@ Geo make_geo(const pbr_ctx* c, int block, const double kappa[3]);
 // with alpha from the (p, q) partials of the matvec (or r = b, x = 0 at init),
 // z the transform buffer, pout = z + beta p (p at init).
 struct PcgStep {
+  int block = -1;
   PcgScalars* st = nullptr;
   int init = 0;
   double tol2 = 0.0;
@@ -123,18 +120,31 @@ struct PcgStep {
   long part_cap = 0;  // capacity of each partial buffer (doubles)
 };
 
-// y = (A + s M) x in layout `block`.  With `st` non-null the launch does nothing
-// once st->done != 0 and writes per-work-group partials of Re(x^H y) to `part`
-// (their number to *nparts).
+// One layout of a batched matvec: y = (A + s M) x in layout `block`.  With st
+// non-null its work-groups do nothing once st->done != 0 and write partials of
+// Re(x^H y) to part.
+struct ApplyLayout {
+  int block = -1;
+  const cplx* x = nullptr;
+  cplx* y = nullptr;
+  PcgScalars* st = nullptr;
+  double* part = nullptr;
+};
+// nb layouts of one kind (all blocks, or the natural layout alone) in one
+// launch; g is the geometry of any of them (the class bits come from L[t].block);
+// *nparts receives the partials per layout.
+int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,
+                       long part_cap = 0, int* nparts = nullptr);
 int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
                  PcgScalars* st = nullptr, double* part = nullptr, long part_cap = 0,
                  int* nparts = nullptr);
 // z = preconditioner(r) in layout `block`
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
                    const cplx* r, cplx* z);
-// the preconditioner passes of one fused PCG iteration (five launches)
-int launch_pcg_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
-                       const PcgStep& P);
+// The preconditioner passes of one fused PCG iteration (five launches) for nb
+// layouts of one kind at once; P[t].block names the layout.
+int launch_pcg_precond_batch(pbr_ctx* c, const double kappa[3], int nb, const PcgStep* P,
+                             double shift);
 
 // solver drivers (solver.cpp)
 int ensure_work(pbr_ctx* c, int block);

@@ -133,9 +133,11 @@ struct LineArgs {
   const cplx* __restrict__ roots;
   const cplx* __restrict__ twist;  // e^{-i y phi / L}, y in [0, L) of the transform
   double scale;
-  const cplx* in;
-  cplx* out;
-  PcgHook h;         // fused PCG work (h.st == nullptr: plain transform)
+  struct {
+    const cplx* in;
+    cplx* out;
+    PcgHook h;       // fused PCG work (h.st == nullptr: plain transform)
+  } b[PBR_MAX_BATCH];  // layout blockIdx.z of the batch
 };
 
 // First work-group of a PCG launch: finish the partials of the previous launch.
@@ -171,7 +173,9 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   constexpr int B = (FFT_ELEMS / LM) > 0 ? FFT_ELEMS / LM : 1;  // lines per work-group
   __shared__ cplx buf0[B * LM], buf1[B * LM];
   __shared__ double red[FFT_THREADS / 64 + 1];
-  const PcgHook& H = A.h;
+  const PcgHook& H = A.b[blockIdx.z].h;
+  const cplx* in_ = A.b[blockIdx.z].in;
+  cplx* out_ = A.b[blockIdx.z].out;
   PcgScalars* st = H.st;
   const bool first_wg = blockIdx.x == 0 && blockIdx.y == 0;
   if (st && !(MODE == 1 && H.init) && st->done) return;  // uniform per work-group
@@ -241,7 +245,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
         }
         rr = fma(x.x, x.x, fma(x.y, x.y, rr));
       } else {
-        x = A.in[idx];
+        x = in_[idx];
       }
       const int slot = SPLIT ? 2 * b + (e & 1) : b;
       const int y = SPLIT ? e >> 1 : e;
@@ -271,9 +275,9 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
       if (SIGN > 0) x = cmul(x, cconj(A.twist[y]));
       const long idx = co + base_of(l0 + b) + e * es;
       if (MODE == 2 && !H.init)
-        A.out[idx] = cfma(beta, A.out[idx], cscale(A.scale, x));
+        out_[idx] = cfma(beta, out_[idx], cscale(A.scale, x));
       else
-        A.out[idx] = cscale(A.scale, x);
+        out_[idx] = cscale(A.scale, x);
     }
   }
 }
@@ -285,7 +289,6 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
 struct SolveArgs {
   int L1, L2, L3;
   long N;
-  int a, c;                        // block class bits
   const cplx* __restrict__ roots;  // length-L3 roots
   const cplx* __restrict__ twist;  // e^{-i y phi3 / L3}
   const cplx* __restrict__ e1;     // e^{i alpha_m} = e^{i (phi1 + 2 pi m)/n1}, m < n1
@@ -294,9 +297,12 @@ struct SolveArgs {
   double cf[3][5];
   double Cref[21];
   double shift_rho;
-  cplx* data;
-  PcgScalars* st;     // fused PCG: skip once converged, write (r, z) partials
-  double* part_out;
+  struct {
+    cplx* data;
+    PcgScalars* st;   // fused PCG: skip once converged, write (r, z) partials
+    double* part_out;
+    int a, c;         // block class bits
+  } b[PBR_MAX_BATCH];   // layout blockIdx.y of the batch
 };
 
 // K(m)^-1 b for the mode whose one-step phases are Ea = e^{i alpha},
@@ -381,7 +387,11 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   constexpr int NL = 3 * BI;  // lines of one work-group: component-major
   __shared__ cplx buf0[NL * L3T], buf1[NL * L3T];
   __shared__ double red[FFT_THREADS / 64 + 1];
-  if (S.st && S.st->done) return;
+  cplx* const data = S.b[blockIdx.y].data;
+  PcgScalars* const st = S.b[blockIdx.y].st;
+  double* const part_out = S.b[blockIdx.y].part_out;
+  const int ca = S.b[blockIdx.y].a, cc = S.b[blockIdx.y].c;
+  if (st && st->done) return;
   const int groups_i = (S.L1 + BI - 1) / BI;
   const int q = blockIdx.x / groups_i;
   const int i0 = (blockIdx.x % groups_i) * BI;
@@ -394,7 +404,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     const int comp = rem / BI, di = rem - comp * BI;
     if (di < bi)
       buf0[(comp * BI + di) * L3T + y] =
-          cmul(S.data[comp * S.N + base + di + y * kstride], S.twist[y]);
+          cmul(data[comp * S.N + base + di + y * kstride], S.twist[y]);
   }
   __syncthreads();
   cplx* f = fft_stages<L3T, 0, 1, -1>(S.roots, buf0, buf1, NL);
@@ -416,7 +426,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     }
   } else {
     // sub-lattice p has offsets o2(p) = (a+p)&1, o3(p) = (a+c+p)&1
-    const int o20 = S.a & 1, o30 = (S.a + S.c) & 1;
+    const int o20 = ca & 1, o30 = (ca + cc) & 1;
     for (int w = threadIdx.x; w < (bi / 2) * L3T; w += blockDim.x) {
       const int dp = w / L3T, r = w - dp * L3T;
       const int m1p = (i0 >> 1) + dp;
@@ -446,9 +456,9 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       }
     }
   }
-  if (S.part_out) {
+  if (part_out) {
     const double v = block_sum_all(rz, red);
-    if (threadIdx.x == 0) S.part_out[blockIdx.x] = v;
+    if (threadIdx.x == 0) part_out[blockIdx.x] = v;
   }
   __syncthreads();
   const cplx* res = fft_stages<L3T, 0, 1, +1>(S.roots, g, f, NL);
@@ -457,7 +467,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     const int rem = w - y * NL;
     const int comp = rem / BI, di = rem - comp * BI;
     if (di < bi)
-      S.data[comp * S.N + base + di + y * kstride] =
+      data[comp * S.N + base + di + y * kstride] =
           cmul(res[(comp * BI + di) * L3T + y], cconj(S.twist[y]));
   }
 }
@@ -477,12 +487,13 @@ __global__ void table_kernel(int L, double phi, int kind, cplx* out) {
   out[t] = mk(c, s);
 }
 
-// Tables per layout: for each transform length Lt[l] (axis 0 of a block: n1/2)
-// the roots and the twist, and the mode phases e^{i(phi_l + 2 pi t)/n_l}.
-int ensure_tables(pbr_ctx* c, int block, const double kappa[3]) {
-  FftTables& T = c->fft[block + 1];
-  const int Lt[3] = {block < 0 ? c->n1 : c->n1 / 2, block < 0 ? c->n2 : c->n2 / 2,
-                     block < 0 ? c->n3 : c->n3 / 2};
+// Tables of a layout kind (natural: slot 0; parity blocks, which share the box
+// shape: slot 1): for each transform length Lt[l] (axis 0 of a block: n1/2) the
+// roots and the twist, and the mode phases e^{i(phi_l + 2 pi t)/n_l}.
+int ensure_tables(pbr_ctx* c, bool blocked, const double kappa[3]) {
+  FftTables& T = c->fft[blocked ? 1 : 0];
+  const int Lt[3] = {blocked ? c->n1 / 2 : c->n1, blocked ? c->n2 / 2 : c->n2,
+                     blocked ? c->n3 / 2 : c->n3};
   const int nf[3] = {c->n1, c->n2, c->n3};
   for (int l = 0; l < 3; ++l) {
     if (!T.roots[l]) {
@@ -490,17 +501,17 @@ int ensure_tables(pbr_ctx* c, int block, const double kappa[3]) {
       PBR_TRY(dev_alloc(c, (void**)&T.roots[l], sizeof(cplx) * Lt[l]));
       PBR_TRY(dev_alloc(c, (void**)&T.twist[l], sizeof(cplx) * Lt[l]));
       PBR_TRY(dev_alloc(c, (void**)&T.post[l], sizeof(cplx) * nf[l]));
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream_of(block), Lt[l],
-                         0.0, 1, T.roots[l]);
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream,
+                         Lt[l], 0.0, 1, T.roots[l]);
     }
   }
   if (T.kappa[0] != kappa[0] || T.kappa[1] != kappa[1] || T.kappa[2] != kappa[2]) {
     for (int l = 0; l < 3; ++l) {
       const double phi = 2.0 * M_PI * kappa[l];
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream_of(block), Lt[l],
-                         phi, 0, T.twist[l]);
-      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream_of(block), nf[l],
-                         phi, 2, T.post[l]);
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream,
+                         Lt[l], phi, 0, T.twist[l]);
+      hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream,
+                         nf[l], phi, 2, T.post[l]);
       T.kappa[l] = kappa[l];
     }
   }
@@ -541,17 +552,24 @@ SolveKernel solve_kernel(int L) {
   }
 }
 
-// One pass of lines along `axis`; mode 1 / 2 are the first / last PCG pass.
-// *nparts receives the number of partials a mode-1 launch writes.
-int run_lines(pbr_ctx* c, int block, int axis, int sign, int mode, const cplx* in, cplx* out,
-              double scale, const PcgHook& h, long part_cap, int* nparts) {
-  FftTables& T = c->fft[block + 1];
-  const long N = c->layout_nodes(block);
+// One pass of lines along `axis` for nb layouts of one kind; mode 1 / 2 are
+// the first / last PCG pass.  *nparts receives the partials per layout that a
+// mode-1 launch writes.
+struct LineIO {
+  const cplx* in;
+  cplx* out;
+  PcgHook h;
+};
+
+int run_lines(pbr_ctx* c, bool blocked, int nb, int axis, int sign, int mode, const LineIO* io,
+              double scale, long part_cap, int* nparts) {
+  FftTables& T = c->fft[blocked ? 1 : 0];
+  const long N = c->layout_nodes(blocked ? 0 : -1);
   LineArgs A;
   A.L1 = c->n1;
-  A.L2 = block < 0 ? c->n2 : c->n2 / 2;
-  A.L3 = block < 0 ? c->n3 : c->n3 / 2;
-  const int split = (axis == 0 && block >= 0) ? 1 : 0;
+  A.L2 = blocked ? c->n2 / 2 : c->n2;
+  A.L3 = blocked ? c->n3 / 2 : c->n3;
+  const int split = (axis == 0 && blocked) ? 1 : 0;
   const int LT = T.L[axis];
   const int LM = split ? 2 * LT : LT;
   A.nlines = N / LM;
@@ -559,9 +577,11 @@ int run_lines(pbr_ctx* c, int block, int axis, int sign, int mode, const cplx* i
   A.roots = T.roots[axis];
   A.twist = T.twist[axis];
   A.scale = scale;
-  A.in = in;
-  A.out = out;
-  A.h = h;
+  for (int t = 0; t < nb; ++t) {
+    A.b[t].in = io[t].in;
+    A.b[t].out = io[t].out;
+    A.b[t].h = io[t].h;
+  }
   LineKernel k = nullptr;
   if (axis == 0 && split) {
     if (sign < 0)
@@ -581,27 +601,32 @@ int run_lines(pbr_ctx* c, int block, int axis, int sign, int mode, const cplx* i
     return ST_EINVAL;
   }
   const int B = std::max(1, FFT_ELEMS / LM);
-  dim3 grid(ceil_div(A.nlines, B), 3);
+  dim3 grid(ceil_div(A.nlines, B), 3, nb);
   if (nparts) *nparts = (int)(grid.x * 3);
   if (mode == 1 && (long)grid.x * 3 > part_cap) {
     c->set_error("grid too large for the PCG partial buffers");
     return ST_EINVAL;
   }
-  hipLaunchKernelGGL(k, grid, dim3(FFT_THREADS), 0, c->stream_of(block), A);
+  hipLaunchKernelGGL(k, grid, dim3(FFT_THREADS), 0, c->stream, A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
 
-int run_solve(pbr_ctx* c, int block, double shift, cplx* z, PcgScalars* st, double* part_out,
-              long part_cap, int* nparts) {
-  FftTables& T = c->fft[block + 1];
+struct SolveIO {
+  int block;
+  cplx* data;
+  PcgScalars* st;
+  double* part_out;
+};
+
+int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift, long part_cap,
+              int* nparts) {
+  FftTables& T = c->fft[blocked ? 1 : 0];
   SolveArgs S;
   S.L1 = c->n1;
-  S.L2 = block < 0 ? c->n2 : c->n2 / 2;
-  S.L3 = block < 0 ? c->n3 : c->n3 / 2;
-  S.N = c->layout_nodes(block);
-  S.a = block >= 0 ? block >> 1 : 0;
-  S.c = block >= 0 ? block & 1 : 0;
+  S.L2 = blocked ? c->n2 / 2 : c->n2;
+  S.L3 = blocked ? c->n3 / 2 : c->n3;
+  S.N = c->layout_nodes(blocked ? 0 : -1);
   S.roots = T.roots[2];
   S.twist = T.twist[2];
   S.e1 = T.post[0];
@@ -611,23 +636,27 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z, PcgScalars* st, doub
     for (int d = 0; d < 5; ++d) S.cf[m][d] = c->cf[m][d];
   for (int qq = 0; qq < 21; ++qq) S.Cref[qq] = c->Cref[qq];
   S.shift_rho = shift * c->rho_ref;
-  S.data = z;
-  S.st = st;
-  S.part_out = part_out;
-  const SolveKernel k = block >= 0 ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
+  for (int t = 0; t < nb; ++t) {
+    S.b[t].data = io[t].data;
+    S.b[t].st = io[t].st;
+    S.b[t].part_out = io[t].part_out;
+    S.b[t].a = io[t].block >= 0 ? io[t].block >> 1 : 0;
+    S.b[t].c = io[t].block >= 0 ? io[t].block & 1 : 0;
+  }
+  const SolveKernel k = blocked ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
   if (!k) {
     c->set_error("FFT lengths must be 2^a 3^b up to 256");
     return ST_EINVAL;
   }
-  const int bi = solve_bi(S.L3, block >= 0 ? 1 : 0);
+  const int bi = solve_bi(S.L3, blocked ? 1 : 0);
   const int groups_i = (S.L1 + bi - 1) / bi;
   const long nwg = (long)groups_i * S.L2;
   if (nparts) *nparts = (int)nwg;
-  if (part_out && nwg > part_cap) {
+  if (io[0].part_out && nwg > part_cap) {
     c->set_error("grid too large for the PCG partial buffers");
     return ST_EINVAL;
   }
-  hipLaunchKernelGGL(k, dim3((unsigned)nwg), dim3(FFT_THREADS), 0, c->stream_of(block), S);
+  hipLaunchKernelGGL(k, dim3((unsigned)nwg, nb), dim3(FFT_THREADS), 0, c->stream, S);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
@@ -636,53 +665,64 @@ int run_solve(pbr_ctx* c, int block, double shift, cplx* z, PcgScalars* st, doub
 
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, const cplx* r,
                    cplx* z) {
-  PBR_TRY(ensure_tables(c, block, kappa));
+  const bool blocked = block >= 0;
+  PBR_TRY(ensure_tables(c, blocked, kappa));
   const long N = c->layout_nodes(block);
-  const PcgHook none;
-  PBR_TRY(run_lines(c, block, 0, -1, 0, r, z, 1.0, none, 0, nullptr));
-  PBR_TRY(run_lines(c, block, 1, -1, 0, z, z, 1.0, none, 0, nullptr));
-  PBR_TRY(run_solve(c, block, shift, z, nullptr, nullptr, 0, nullptr));
-  PBR_TRY(run_lines(c, block, 1, +1, 0, z, z, 1.0, none, 0, nullptr));
-  PBR_TRY(run_lines(c, block, 0, +1, 0, z, z, 1.0 / (double)N, none, 0, nullptr));
+  LineIO a{r, z, PcgHook()}, b{z, z, PcgHook()};
+  SolveIO s{block, z, nullptr, nullptr};
+  PBR_TRY(run_lines(c, blocked, 1, 0, -1, 0, &a, 1.0, 0, nullptr));
+  PBR_TRY(run_lines(c, blocked, 1, 1, -1, 0, &b, 1.0, 0, nullptr));
+  PBR_TRY(run_solve(c, blocked, 1, &s, shift, 0, nullptr));
+  PBR_TRY(run_lines(c, blocked, 1, 1, +1, 0, &b, 1.0, 0, nullptr));
+  PBR_TRY(run_lines(c, blocked, 1, 0, +1, 0, &b, 1.0 / (double)N, 0, nullptr));
   return ST_OK;
 }
 
-int launch_pcg_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
-                       const PcgStep& P) {
-  PBR_TRY(ensure_tables(c, block, kappa));
-  const long N = c->layout_nodes(block);
-  PcgHook h;
-  h.st = P.st;
-  h.init = P.init;
-  h.tol2 = P.tol2;
-  h.inv_n = 1.0 / (double)N;
+int launch_pcg_precond_batch(pbr_ctx* c, const double kappa[3], int nb, const PcgStep* P,
+                             double shift) {
+  if (nb < 1 || nb > PBR_MAX_BATCH) {
+    c->set_error("batch of 1 to 4 layouts expected");
+    return ST_EINVAL;
+  }
+  const bool blocked = P[0].block >= 0;
+  PBR_TRY(ensure_tables(c, blocked, kappa));
+  const long N = c->layout_nodes(P[0].block);
+  const long cap = P[0].part_cap;
+  LineIO io1[PBR_MAX_BATCH], io2[PBR_MAX_BATCH], io4[PBR_MAX_BATCH], io5[PBR_MAX_BATCH];
+  SolveIO sio[PBR_MAX_BATCH];
   int n_rr = 0, n_rz = 0;
-  // pass 1: update (or initialise) x and r, |r|^2 partials, forward lines of r
-  PcgHook h1 = h;
-  h1.x = P.x;
-  h1.r = P.r;
-  h1.p = P.p;
-  h1.q = P.q;
-  h1.b = P.b;
-  h1.red_in = P.part_pq;
-  h1.red_n = P.n_pq;
-  h1.part_out = P.part_rr;
-  PBR_TRY(run_lines(c, block, 0, -1, 1, nullptr, P.z, 1.0, h1, P.part_cap, &n_rr));
-  // pass 2: first work-group finishes |r|^2 and the convergence test
-  PcgHook h2 = h;
-  h2.role = 1;
-  h2.red_in = P.part_rr;
-  h2.red_n = n_rr;
-  PBR_TRY(run_lines(c, block, 1, -1, 0, P.z, P.z, 1.0, h2, P.part_cap, nullptr));
-  // pass 3: mode solve with (r, z) partials
-  PBR_TRY(run_solve(c, block, shift, P.z, P.st, P.part_rz, P.part_cap, &n_rz));
-  // pass 4: first work-group finishes (r, z) and beta
-  PcgHook h4 = h;
-  h4.role = 2;
-  h4.red_in = P.part_rz;
-  h4.red_n = n_rz;
-  PBR_TRY(run_lines(c, block, 1, +1, 0, P.z, P.z, 1.0, h4, P.part_cap, nullptr));
-  // pass 5: p = z + beta p
-  PBR_TRY(run_lines(c, block, 0, +1, 2, P.z, P.pout, 1.0 / (double)N, h, P.part_cap, nullptr));
+  for (int t = 0; t < nb; ++t) {
+    PcgHook h;
+    h.st = P[t].st;
+    h.init = P[t].init;
+    h.tol2 = P[t].tol2;
+    h.inv_n = 1.0 / (double)N;
+    // pass 1: update (or initialise) x and r, |r|^2 partials, forward lines of r
+    PcgHook h1 = h;
+    h1.x = P[t].x;
+    h1.r = P[t].r;
+    h1.p = P[t].p;
+    h1.q = P[t].q;
+    h1.b = P[t].b;
+    h1.red_in = P[t].part_pq;
+    h1.red_n = P[t].n_pq;
+    h1.part_out = P[t].part_rr;
+    io1[t] = LineIO{nullptr, P[t].z, h1};
+    io2[t] = LineIO{P[t].z, P[t].z, h};
+    io2[t].h.role = 1;  // first work-group finishes |r|^2 and the convergence test
+    io2[t].h.red_in = P[t].part_rr;
+    io4[t] = LineIO{P[t].z, P[t].z, h};
+    io4[t].h.role = 2;  // first work-group finishes (r, z) and beta
+    io4[t].h.red_in = P[t].part_rz;
+    io5[t] = LineIO{P[t].z, P[t].pout, h};  // p = z + beta p
+    sio[t] = SolveIO{P[t].block, P[t].z, P[t].st, P[t].part_rz};
+  }
+  PBR_TRY(run_lines(c, blocked, nb, 0, -1, 1, io1, 1.0, cap, &n_rr));
+  for (int t = 0; t < nb; ++t) io2[t].h.red_n = n_rr;
+  PBR_TRY(run_lines(c, blocked, nb, 1, -1, 0, io2, 1.0, cap, nullptr));
+  PBR_TRY(run_solve(c, blocked, nb, sio, shift, cap, &n_rz));
+  for (int t = 0; t < nb; ++t) io4[t].h.red_n = n_rz;
+  PBR_TRY(run_lines(c, blocked, nb, 1, +1, 0, io4, 1.0, cap, nullptr));
+  PBR_TRY(run_lines(c, blocked, nb, 0, +1, 2, io5, 1.0 / (double)N, cap, nullptr));
   return ST_OK;
 }

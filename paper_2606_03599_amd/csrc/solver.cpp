@@ -13,7 +13,6 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
-#include <thread>
 #include <vector>
 
 #include "../../include/pbr_host.h"
@@ -46,28 +45,32 @@ bool is_gamma(const double k[3]) {
   return true;
 }
 
-// Read `count` doubles from device to host (synchronises the layout's stream).
-int readback(pbr_ctx* c, LayoutWork& W, const double* dev, double* host, int count) {
-  const hipStream_t SO = c->stream_of(W.block);
-  PBR_HIP(c, hipMemcpyAsync(W.hpin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, SO));
-  PBR_HIP(c, hipStreamSynchronize(SO));
-  for (int i = 0; i < count; ++i) host[i] = W.hpin[i];
+// Read `count` doubles from device to host (synchronises the stream).
+int readback(pbr_ctx* c, const double* dev, double* host, int count) {
+  if (count > PBR_PINNED) {
+    c->set_error("readback larger than the pinned staging buffer");
+    return ST_EINVAL;
+  }
+  PBR_HIP(c, hipMemcpyAsync(c->hpinned, dev, sizeof(double) * count, hipMemcpyDeviceToHost,
+                            c->stream));
+  PBR_HIP(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < count; ++i) host[i] = c->hpinned[i];
   return ST_OK;
 }
 
-int upload_small(pbr_ctx* c, LayoutWork& W, cplx* dev, const std::vector<zc>& h) {
-  if ((long)h.size() > SMALL_CPLX) {
+int upload_small(pbr_ctx* c, cplx* dev, const std::vector<zc>& h) {
+  if ((long)h.size() > SMALL_CPLX || 2 * (long)h.size() > PBR_PINNED) {
     c->set_error("Krylov basis too large for the small-matrix buffer");
     return ST_EINVAL;
   }
-  const hipStream_t SO = c->stream_of(W.block);
   for (size_t i = 0; i < h.size(); ++i) {
-    W.hpin[2 * i] = h[i].real();
-    W.hpin[2 * i + 1] = h[i].imag();
+    c->hpinned[2 * i] = h[i].real();
+    c->hpinned[2 * i + 1] = h[i].imag();
   }
-  PBR_HIP(c, hipMemcpyAsync(dev, W.hpin, sizeof(cplx) * h.size(), hipMemcpyHostToDevice, SO));
+  PBR_HIP(c, hipMemcpyAsync(dev, c->hpinned, sizeof(cplx) * h.size(), hipMemcpyHostToDevice,
+                            c->stream));
   // the pinned staging buffer is reused by the next call: wait for the copy
-  PBR_HIP(c, hipStreamSynchronize(SO));
+  PBR_HIP(c, hipStreamSynchronize(c->stream));
   return ST_OK;
 }
 
@@ -157,22 +160,21 @@ int ensure_null_fields(pbr_ctx* c, int block) {
     for (long t = 0; t < N; ++t) F[t] = std::sqrt(rho[t] / sr);
   }
   PBR_TRY(dev_alloc(c, (void**)&W.Wnull, sizeof(double) * nf * N));
-  const hipStream_t SO = c->stream_of(block);
   PBR_HIP(c, hipMemcpyAsync(W.Wnull, F.data(), sizeof(double) * nf * N, hipMemcpyHostToDevice,
-                            SO));
-  PBR_HIP(c, hipStreamSynchronize(SO));
+                            c->stream));
+  PBR_HIP(c, hipStreamSynchronize(c->stream));
   W.nf = nf;
   return ST_OK;
 }
 
 int project_null(pbr_ctx* c, LayoutWork& W, cplx* v) {
-  return proj_gamma(c, c->stream_of(W.block), W.N, W.nf, W.Wnull, v, W.part, W.dscal);
+  return proj_gamma(c, c->stream, W.N, W.nf, W.Wnull, v, W.part, W.dscal);
 }
 
 double vnorm(pbr_ctx* c, LayoutWork& W, const cplx* v, int* status) {
   double h;
-  int s = dot_real_async(c, c->stream_of(W.block), 3 * W.N, v, v, W.part, W.dscal);
-  if (s == ST_OK) s = readback(c, W, W.dscal, &h, 1);
+  int s = dot_real_async(c, c->stream, 3 * W.N, v, v, W.part, W.dscal);
+  if (s == ST_OK) s = readback(c, W.dscal, &h, 1);
   *status = s;
   return std::sqrt(std::max(h, 0.0));
 }
@@ -198,89 +200,139 @@ int ensure_work(pbr_ctx* c, int block) {
   PBR_TRY(dev_alloc(c, (void**)&W.part, sizeof(double) * 1024 * 2 * 128));
   PBR_TRY(dev_alloc(c, (void**)&W.part2, sizeof(double) * 1024 * 2));
   PBR_TRY(dev_alloc(c, (void**)&W.dscal, sizeof(double) * 4096));
-  PBR_TRY(dev_alloc(c, (void**)&W.st, sizeof(PcgScalars)));
+  if (!c->st_all) PBR_TRY(dev_alloc(c, (void**)&c->st_all, sizeof(PcgScalars) * 5));
+  W.st = c->st_all + (block + 1);
   W.pcap = N / 128 + 4096;
   PBR_TRY(dev_alloc(c, (void**)&W.ppart, sizeof(double) * 3 * W.pcap));
-  if (!W.hpin) PBR_HIP(c, hipHostMalloc((void**)&W.hpin, sizeof(double) * 32768));
   return ST_OK;
+}
+
+namespace {
+
+// Device CG scalars of all five layouts in one copy.
+int read_states(pbr_ctx* c, PcgScalars hs[5]) {
+  PBR_HIP(c, hipMemcpyAsync(c->hpinned, c->st_all, sizeof(PcgScalars) * 5,
+                            hipMemcpyDeviceToHost, c->stream));
+  PBR_HIP(c, hipStreamSynchronize(c->stream));
+  std::memcpy(hs, c->hpinned, sizeof(PcgScalars) * 5);
+  return ST_OK;
+}
+
+// Unpreconditioned CG of one layout (kept for pbr_opts.precond = 0).
+int pcg_plain(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b,
+              cplx* x, const pbr_opts& o) {
+  LayoutWork& W = c->work[block + 1];
+  const hipStream_t SO = c->stream;
+  const long n3 = 3 * W.N;
+  const Geo g = make_geo(c, block, kappa);
+  const int chunk = o.check_every > 0 ? o.check_every : 10;
+  PBR_TRY(vec_zero(c, SO, n3, x));
+  PBR_TRY(vec_copy(c, SO, n3, b, W.r));
+  PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
+  PBR_TRY(vec_copy(c, SO, n3, W.z, W.p));
+  PBR_TRY(pcg_init_async(c, SO, n3, W.r, W.z, o.tol_inner, W.part, W.part2, W.st));
+  int done_iters = 0;
+  PcgScalars hs[5];
+  for (;;) {
+    const int todo = std::min(chunk, o.maxit_inner - done_iters);
+    if (todo <= 0) break;
+    for (int it = 0; it < todo; ++it) {
+      PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q, W.st));
+      PBR_TRY(pcg_alpha(c, SO, n3, W.p, W.q, W.part, W.st));
+      PBR_TRY(pcg_xr(c, SO, n3, x, W.r, W.p, W.q, W.part, W.st));
+      PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
+      PBR_TRY(pcg_beta_p(c, SO, n3, W.r, W.z, W.p, W.part, W.st));
+    }
+    PBR_TRY(read_states(c, hs));
+    done_iters = hs[block + 1].iters;
+    if (hs[block + 1].done) break;
+  }
+  return ST_OK;
+}
+
+}  // namespace
+
+// PCG for (A + shift M) x_t = b_t in nb layouts of one kind at once: every
+// launch of an iteration covers all of them, and a layout that has converged
+// drops out through its device flag.  Results per layout in iters[] / conv[];
+// returns ST_ENOCONV on a breakdown.
+int pcg_solve_batch(pbr_ctx* c, int nb, const int* blocks, const double kappa[3], double shift,
+                    const cplx* const* b, cplx* const* x, const pbr_opts& o, int* iters,
+                    int* conv) {
+  for (int t = 0; t < nb; ++t) PBR_TRY(ensure_work(c, blocks[t]));
+  PcgScalars hs[5];
+  if (!o.precond) {
+    for (int t = 0; t < nb; ++t) PBR_TRY(pcg_plain(c, blocks[t], kappa, shift, b[t], x[t], o));
+  } else {
+    // fused iteration: matvec (+ (p, q) partials) and five preconditioner passes
+    // that also update x, r and p and finish the CG scalars on the device
+    const Geo g = make_geo(c, blocks[0], kappa);
+    PcgStep P[PBR_MAX_BATCH];
+    ApplyLayout AL[PBR_MAX_BATCH];
+    for (int t = 0; t < nb; ++t) {
+      LayoutWork& W = c->work[blocks[t] + 1];
+      P[t].block = blocks[t];
+      P[t].st = W.st;
+      P[t].tol2 = o.tol_inner * o.tol_inner;
+      P[t].x = x[t];
+      P[t].r = W.r;
+      P[t].p = W.p;
+      P[t].q = W.q;
+      P[t].b = b[t];
+      P[t].z = W.z;
+      P[t].pout = W.p;
+      P[t].part_pq = W.ppart;
+      P[t].part_rr = W.ppart + W.pcap;
+      P[t].part_rz = W.ppart + 2 * W.pcap;
+      P[t].part_cap = W.pcap;
+      P[t].init = 1;
+      AL[t].block = blocks[t];
+      AL[t].x = W.p;
+      AL[t].y = W.q;
+      AL[t].st = W.st;
+      AL[t].part = W.ppart;
+    }
+    PBR_TRY(launch_pcg_precond_batch(c, kappa, nb, P, shift));
+    for (int t = 0; t < nb; ++t) P[t].init = 0;
+    const int chunk = o.check_every > 0 ? o.check_every : 10;
+    int done_iters = 0;
+    for (;;) {
+      const int todo = std::min(chunk, o.maxit_inner - done_iters);
+      if (todo <= 0) break;
+      for (int it = 0; it < todo; ++it) {
+        int npq = 0;
+        PBR_TRY(launch_apply_batch(c, g, nb, AL, shift, P[0].part_cap, &npq));
+        for (int t = 0; t < nb; ++t) P[t].n_pq = npq;
+        PBR_TRY(launch_pcg_precond_batch(c, kappa, nb, P, shift));
+      }
+      PBR_TRY(read_states(c, hs));
+      bool all = true;
+      done_iters = 0;
+      for (int t = 0; t < nb; ++t) {
+        const PcgScalars& h = hs[blocks[t] + 1];
+        done_iters = std::max(done_iters, h.iters);
+        all = all && h.done;
+      }
+      if (all) break;
+    }
+  }
+  PBR_TRY(read_states(c, hs));
+  int status = ST_OK;
+  for (int t = 0; t < nb; ++t) {
+    const PcgScalars& h = hs[blocks[t] + 1];
+    iters[t] = h.iters;
+    conv[t] = (h.done == 1) ? 1 : 0;
+    if (h.done == 2) {
+      c->set_error("PCG breakdown: (p, (A + shift M) p) <= 0");
+      status = ST_ENOCONV;
+    }
+  }
+  return status;
 }
 
 int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b, cplx* x,
               const pbr_opts& o, int* iters, int* conv) {
-  PBR_TRY(ensure_work(c, block));
-  LayoutWork& W = c->work[block + 1];
-  const hipStream_t SO = c->stream_of(block);
-  const long n3 = 3 * W.N;
-  const Geo g = make_geo(c, block, kappa);
-  const int chunk = o.check_every > 0 ? o.check_every : 10;
-  int done_iters = 0;
-  PcgScalars hs;
-  auto read_state = [&]() -> int {
-    PBR_HIP(c, hipMemcpyAsync(W.hpin, W.st, sizeof(PcgScalars), hipMemcpyDeviceToHost, SO));
-    PBR_HIP(c, hipStreamSynchronize(SO));
-    std::memcpy(&hs, W.hpin, sizeof(PcgScalars));
-    return ST_OK;
-  };
-  if (o.precond) {
-    // fused iteration: matvec (+ (p, q) partials) and five preconditioner passes
-    // that also update x, r and p and finish the CG scalars on the device
-    PcgStep P;
-    P.st = W.st;
-    P.tol2 = o.tol_inner * o.tol_inner;
-    P.x = x;
-    P.r = W.r;
-    P.p = W.p;
-    P.q = W.q;
-    P.b = b;
-    P.z = W.z;
-    P.pout = W.p;
-    P.part_pq = W.ppart;
-    P.part_rr = W.ppart + W.pcap;
-    P.part_rz = W.ppart + 2 * W.pcap;
-    P.part_cap = W.pcap;
-    P.init = 1;
-    PBR_TRY(launch_pcg_precond(c, kappa, block, shift, P));
-    P.init = 0;
-    for (;;) {
-      const int todo = std::min(chunk, o.maxit_inner - done_iters);
-      if (todo <= 0) break;
-      for (int it = 0; it < todo; ++it) {
-        PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q, W.st, W.ppart, W.pcap, &P.n_pq));
-        PBR_TRY(launch_pcg_precond(c, kappa, block, shift, P));
-      }
-      PBR_TRY(read_state());
-      done_iters = hs.iters;
-      if (hs.done) break;
-    }
-  } else {
-    PBR_TRY(vec_zero(c, SO, n3, x));
-    PBR_TRY(vec_copy(c, SO, n3, b, W.r));
-    PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
-    PBR_TRY(vec_copy(c, SO, n3, W.z, W.p));
-    PBR_TRY(pcg_init_async(c, SO, n3, W.r, W.z, o.tol_inner, W.part, W.part2, W.st));
-    for (;;) {
-      const int todo = std::min(chunk, o.maxit_inner - done_iters);
-      if (todo <= 0) break;
-      for (int it = 0; it < todo; ++it) {
-        PBR_TRY(launch_apply(c, g, block, shift, W.p, W.q, W.st));
-        PBR_TRY(pcg_alpha(c, SO, n3, W.p, W.q, W.part, W.st));
-        PBR_TRY(pcg_xr(c, SO, n3, x, W.r, W.p, W.q, W.part, W.st));
-        PBR_TRY(vec_copy(c, SO, n3, W.r, W.z));
-        PBR_TRY(pcg_beta_p(c, SO, n3, W.r, W.z, W.p, W.part, W.st));
-      }
-      PBR_TRY(read_state());
-      done_iters = hs.iters;
-      if (hs.done) break;
-    }
-  }
-  PBR_TRY(read_state());
-  *iters = hs.iters;
-  *conv = (hs.done == 1) ? 1 : 0;
-  if (hs.done == 2) {
-    c->set_error("PCG breakdown: (p, (A + shift M) p) <= 0");
-    return ST_ENOCONV;
-  }
-  return ST_OK;
+  return pcg_solve_batch(c, 1, &block, kappa, shift, &b, &x, o, iters, conv);
 }
 
 namespace {
@@ -289,42 +341,67 @@ struct OpCounters {
   int applies = 0, pcg_total = 0, pcg_max = 0, matvecs = 0, pcg_fail = 0;
 };
 
-// w = M^{1/2} (A + shift M)^{-1} M^{1/2} u
-int op_apply(pbr_ctx* c, int block, const double kappa[3], double shift, const pbr_opts& o,
-             const cplx* u, cplx* w, OpCounters& cnt) {
-  LayoutWork& W = c->work[block + 1];
-  DevMaterial& M = c->material(block);
-  const hipStream_t SO = c->stream_of(block);
-  PBR_TRY(vec_diag_scale(c, SO, W.N, M.srho, u, W.b));
-  int it = 0, conv = 0;
-  int s = pcg_solve(c, block, kappa, shift, W.b, W.t, o, &it, &conv);
-  if (s != ST_OK && s != ST_ENOCONV) return s;
-  cnt.applies += 1;
-  cnt.pcg_total += it;
-  cnt.pcg_max = std::max(cnt.pcg_max, it);
-  cnt.matvecs += it;
-  if (!conv) cnt.pcg_fail += 1;
-  PBR_TRY(vec_diag_scale(c, SO, W.N, M.srho, W.t, w));
+// State of one thick-restart Lanczos run (one layout).  The runs of a batch
+// advance in lockstep: each step is one shift-invert application, done for all
+// active runs by one batched PCG.
+struct LanczosRun {
+  int block = -1, nev = 0, m = 0, ldh = 0;
+  bool gamma = false;
+  long N = 0, n3 = 0, ld = 0;
+  int n_zero = 0;
+  int j = 0, restarts = 0, nconv = 0;
+  bool exhausted = false, done = false;
+  int status = ST_OK;
+  std::vector<zc> H;  // column-major, leading dimension ldh
+  std::vector<double> beta, theta, Yr, Hd, hbuf;
+  std::vector<int> order;
+  OpCounters cnt;
+  std::chrono::steady_clock::time_point t0;
+};
+
+// Rayleigh-Ritz on the leading mm x mm block of H; the Ritz residuals of the
+// Krylov-Schur relation are |b_last * (last entry of the Ritz vector)|.
+int lz_ritz(pbr_ctx* c, LanczosRun& R, int mm, double bl, const pbr_opts& o) {
+  for (int jj = 0; jj < mm; ++jj)
+    for (int ii = 0; ii < mm; ++ii) {
+      R.Hd[2 * ((size_t)jj * mm + ii)] = R.H[(size_t)jj * R.ldh + ii].real();
+      R.Hd[2 * ((size_t)jj * mm + ii) + 1] = R.H[(size_t)jj * R.ldh + ii].imag();
+    }
+  if (pbr_host_heev(mm, R.Hd.data(), R.theta.data(), R.Yr.data()) != 0) {
+    c->set_error("Rayleigh-Ritz eigensolver failed");
+    return ST_EINVAL;
+  }
+  R.order.resize(mm);
+  for (int i = 0; i < mm; ++i) R.order[i] = mm - 1 - i;  // largest mu first
+  R.nconv = 0;
+  for (int i = 0; i < std::min(R.nev, mm); ++i) {
+    const int col = R.order[i];
+    const zc ylast(R.Yr[2 * ((size_t)col * mm + (mm - 1))],
+                   R.Yr[2 * ((size_t)col * mm + (mm - 1)) + 1]);
+    if (bl * std::abs(ylast) <= o.tol * std::abs(R.theta[col]))
+      ++R.nconv;
+    else
+      break;
+  }
   return ST_OK;
 }
 
-}  // namespace
-
-int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double shift,
-                 const pbr_opts& o, double* evals, cplx* evecs_dev, pbr_stats* st) {
-  auto t0 = std::chrono::steady_clock::now();
+int lz_start(pbr_ctx* c, LanczosRun& R, int block, int nev, const double kappa[3],
+             const pbr_opts& o) {
+  R.t0 = std::chrono::steady_clock::now();
   PBR_TRY(ensure_work(c, block));
   LayoutWork& W = c->work[block + 1];
-  DevMaterial& M = c->material(block);
-  const hipStream_t SO = c->stream_of(block);
-  const long N = W.N, n3 = 3 * N;
-  const bool gamma = is_gamma(kappa);
-  int n_zero = 0;
-  if (gamma) {
+  R.block = block;
+  R.nev = nev;
+  R.N = W.N;
+  R.n3 = 3 * W.N;
+  R.ld = R.n3;
+  R.gamma = is_gamma(kappa);
+  if (R.gamma) {
     PBR_TRY(ensure_null_fields(c, block));
-    n_zero = 3 * W.nf;
+    R.n_zero = 3 * W.nf;
   }
-  const long dim_eff = n3 - n_zero;
+  const long dim_eff = R.n3 - R.n_zero;
   if (nev < 1 || nev >= dim_eff) {
     c->set_error("nev must satisfy 1 <= nev < dim - n_zero");
     return ST_EINVAL;
@@ -332,174 +409,169 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
   int m = o.ncv > 0 ? o.ncv : std::max(2 * nev + 10, 20);
   if (m > dim_eff) m = (int)dim_eff;
   if (m < nev + 1) m = nev + 1;
-  if ((long)m * m > SMALL_CPLX || m > 120) {
+  if ((long)m * m > SMALL_CPLX || m > 90) {
     c->set_error("Krylov basis size ncv too large (at most 90)");
     return ST_EINVAL;
   }
+  R.m = R.ldh = m;
   PBR_TRY(ensure_basis(c, W, m + 1));
-  const long ld = n3;
-  OpCounters cnt;
-  int st_err;
+  R.H.assign((size_t)m * m, zc(0, 0));
+  R.beta.assign(m, 0.0);
+  R.theta.assign(m, 0.0);
+  R.Yr.assign(2 * (size_t)m * m, 0.0);
+  R.Hd.assign(2 * (size_t)m * m, 0.0);
+  R.hbuf.assign(4 * m + 8, 0.0);
   // start vector
-  PBR_TRY(vec_random(c, SO, n3, (unsigned long long)(o.seed * 7919 + 17 + block), W.U));
-  if (gamma) PBR_TRY(project_null(c, W, W.U));
-  double nrm = vnorm(c, W, W.U, &st_err);
+  const hipStream_t SO = c->stream;
+  int st_err;
+  PBR_TRY(vec_random(c, SO, R.n3, (unsigned long long)(o.seed * 7919 + 17 + block), W.U));
+  if (R.gamma) PBR_TRY(project_null(c, W, W.U));
+  const double nrm = vnorm(c, W, W.U, &st_err);
   PBR_TRY(st_err);
-  PBR_TRY(vec_scale(c, SO, n3, W.U, 1.0 / nrm));
+  PBR_TRY(vec_scale(c, SO, R.n3, W.U, 1.0 / nrm));
+  R.j = 0;
+  return ST_OK;
+}
 
-  std::vector<zc> H((size_t)m * m, zc(0, 0));  // column-major, leading dimension ldh
-  const int ldh = m;
-  std::vector<double> beta(m, 0.0);
-  std::vector<double> theta(m);
-  std::vector<double> Yr(2 * (size_t)m * m);
-  std::vector<double> Hd(2 * (size_t)m * m);
-  std::vector<double> hbuf(4 * m + 8);
-  int j0 = 0;
-  int restarts = 0;
-  int nconv = 0;
-  bool exhausted = false;
-  std::vector<int> order;
-  // Rayleigh-Ritz on the leading mm x mm block of H; the Ritz residuals of the
-  // Krylov-Schur relation are |b_last * (last entry of the Ritz vector)|.
-  auto ritz = [&](int mm, double bl) -> int {
-    for (int jj = 0; jj < mm; ++jj)
-      for (int ii = 0; ii < mm; ++ii) {
-        Hd[2 * ((size_t)jj * mm + ii)] = H[(size_t)jj * ldh + ii].real();
-        Hd[2 * ((size_t)jj * mm + ii) + 1] = H[(size_t)jj * ldh + ii].imag();
-      }
-    if (pbr_host_heev(mm, Hd.data(), theta.data(), Yr.data()) != 0) {
-      c->set_error("Rayleigh-Ritz eigensolver failed");
-      return ST_EINVAL;
+// Continue run R after W.w = Op u_j: orthogonalise, extend H, test convergence,
+// restart when the basis is full.
+int lz_step(pbr_ctx* c, LanczosRun& R, const pbr_opts& o) {
+  LayoutWork& W = c->work[R.block + 1];
+  const hipStream_t SO = c->stream;
+  const int j = R.j;
+  const long n3 = R.n3, ld = R.ld;
+  int st_err;
+  if (R.gamma) PBR_TRY(project_null(c, W, W.w));
+  // classical Gram-Schmidt, twice
+  std::vector<zc> h(j + 1, zc(0, 0));
+  for (int pass = 0; pass < 2; ++pass) {
+    PBR_TRY(multi_dot_async(c, SO, n3, j + 1, W.U, ld, W.w, W.part, W.dscal));
+    PBR_TRY(readback(c, W.dscal, R.hbuf.data(), 2 * (j + 1)));
+    std::vector<zc> hp(j + 1);
+    for (int i = 0; i <= j; ++i) {
+      hp[i] = zc(R.hbuf[2 * i], R.hbuf[2 * i + 1]);
+      h[i] += hp[i];
     }
-    order.resize(mm);
-    for (int i = 0; i < mm; ++i) order[i] = mm - 1 - i;  // largest mu first
-    nconv = 0;
-    for (int i = 0; i < std::min(nev, mm); ++i) {
-      const int col = order[i];
-      const zc ylast(Yr[2 * ((size_t)col * mm + (mm - 1))],
-                     Yr[2 * ((size_t)col * mm + (mm - 1)) + 1]);
-      if (bl * std::abs(ylast) <= o.tol * std::abs(theta[col]))
-        ++nconv;
-      else
-        break;
-    }
-    return ST_OK;
-  };
-  for (;;) {
-    bool early = false;
-    for (int j = j0; j < m; ++j) {
-      cplx* uj = W.U + (long)j * ld;
-      PBR_TRY(op_apply(c, block, kappa, shift, o, uj, W.w, cnt));
-      if (gamma) PBR_TRY(project_null(c, W, W.w));
-      // classical Gram-Schmidt, twice
-      std::vector<zc> h(j + 1, zc(0, 0));
-      for (int pass = 0; pass < 2; ++pass) {
-        PBR_TRY(multi_dot_async(c, SO, n3, j + 1, W.U, ld, W.w, W.part, W.dscal));
-        PBR_TRY(readback(c, W, W.dscal, hbuf.data(), 2 * (j + 1)));
-        std::vector<zc> hp(j + 1);
-        for (int i = 0; i <= j; ++i) {
-          hp[i] = zc(hbuf[2 * i], hbuf[2 * i + 1]);
-          h[i] += hp[i];
-        }
-        PBR_TRY(upload_small(c, W, W.small, hp));
-        PBR_TRY(gemv_sub(c, SO, n3, j + 1, W.U, ld, W.small, W.w));
-      }
-      if (gamma) PBR_TRY(project_null(c, W, W.w));
-      const double b = vnorm(c, W, W.w, &st_err);
-      PBR_TRY(st_err);
-      for (int i = 0; i <= j; ++i) {
-        H[(size_t)j * ldh + i] = h[i];
-        H[(size_t)i * ldh + j] = std::conj(h[i]);
-      }
-      H[(size_t)j * ldh + j] = zc(h[j].real(), 0.0);
-      beta[j] = b;
-      if (j + 1 < m) {
-        H[(size_t)j * ldh + (j + 1)] = b;
-        H[(size_t)(j + 1) * ldh + j] = b;
-      }
-      cplx* un = W.U + (long)(j + 1) * ld;
-      if (b > 1e-14 * std::abs(h[j]) && b > 0.0) {
-        PBR_TRY(vec_copy(c, SO, n3, W.w, un));
-        PBR_TRY(vec_scale(c, SO, n3, un, 1.0 / b));
-      } else {
-        // invariant subspace: the Ritz values of H are exact
-        beta[j] = 0.0;
-        if (j + 1 < m) {
-          H[(size_t)j * ldh + (j + 1)] = 0.0;
-          H[(size_t)(j + 1) * ldh + j] = 0.0;
-        }
-        m = j + 1;
-        exhausted = true;
-        break;
-      }
-      // convergence test after every step once the basis exceeds nev: stop
-      // as soon as the wanted Ritz pairs have converged
-      if (j + 1 > nev && j + 1 < m) {
-        PBR_TRY(ritz(j + 1, beta[j]));
-        if (nconv >= nev) {
-          m = j + 1;
-          early = true;
-          break;
-        }
-      }
-    }
-    if (!early) PBR_TRY(ritz(m, beta[m - 1]));
-    if (nconv >= nev || exhausted || restarts >= o.maxit_outer) break;
-    // thick restart: keep kk Ritz vectors
-    int kk = nev + (m - nev) / 2;
-    if (kk >= m) kk = m - 1;
-    std::vector<zc> Yk((size_t)m * kk);
-    for (int cc = 0; cc < kk; ++cc)
-      for (int r = 0; r < m; ++r) {
-        const int col = order[cc];
-        Yk[(size_t)cc * m + r] = zc(Yr[2 * ((size_t)col * m + r)], Yr[2 * ((size_t)col * m + r) + 1]);
-      }
-    PBR_TRY(upload_small(c, W, W.small, Yk));
-    PBR_TRY(combine(c, SO, n3, m, kk, W.U, ld, W.small, W.U2, ld));
-    PBR_TRY(vec_copy(c, SO, n3, W.U + (long)m * ld, W.U2 + (long)kk * ld));
-    std::swap(W.U, W.U2);
-    std::fill(H.begin(), H.end(), zc(0, 0));
-    for (int i = 0; i < kk; ++i) H[(size_t)i * ldh + i] = theta[order[i]];
-    j0 = kk;
-    ++restarts;
+    PBR_TRY(upload_small(c, W.small, hp));
+    PBR_TRY(gemv_sub(c, SO, n3, j + 1, W.U, ld, W.small, W.w));
   }
-  // Ritz vectors of the nev largest mu
-  const int nout = std::min(nev, m);
+  if (R.gamma) PBR_TRY(project_null(c, W, W.w));
+  const double b = vnorm(c, W, W.w, &st_err);
+  PBR_TRY(st_err);
+  const int ldh = R.ldh;
+  for (int i = 0; i <= j; ++i) {
+    R.H[(size_t)j * ldh + i] = h[i];
+    R.H[(size_t)i * ldh + j] = std::conj(h[i]);
+  }
+  R.H[(size_t)j * ldh + j] = zc(h[j].real(), 0.0);
+  R.beta[j] = b;
+  if (j + 1 < R.m) {
+    R.H[(size_t)j * ldh + (j + 1)] = b;
+    R.H[(size_t)(j + 1) * ldh + j] = b;
+  }
+  cplx* un = W.U + (long)(j + 1) * ld;
+  if (b > 1e-14 * std::abs(h[j]) && b > 0.0) {
+    PBR_TRY(vec_copy(c, SO, n3, W.w, un));
+    PBR_TRY(vec_scale(c, SO, n3, un, 1.0 / b));
+  } else {
+    // invariant subspace: the Ritz values of H are exact
+    R.beta[j] = 0.0;
+    if (j + 1 < R.m) {
+      R.H[(size_t)j * ldh + (j + 1)] = 0.0;
+      R.H[(size_t)(j + 1) * ldh + j] = 0.0;
+    }
+    R.m = j + 1;
+    R.exhausted = true;
+    PBR_TRY(lz_ritz(c, R, R.m, 0.0, o));
+    R.done = true;
+    return ST_OK;
+  }
+  // convergence test after every step once the basis exceeds nev: stop as soon
+  // as the wanted Ritz pairs have converged
+  if (j + 1 > R.nev && j + 1 < R.m) {
+    PBR_TRY(lz_ritz(c, R, j + 1, R.beta[j], o));
+    if (R.nconv >= R.nev) {
+      R.m = j + 1;
+      R.done = true;
+      return ST_OK;
+    }
+  }
+  if (j + 1 < R.m) {
+    R.j = j + 1;
+    return ST_OK;
+  }
+  // basis full: Rayleigh-Ritz, then stop or thick-restart with kk Ritz vectors
+  const int m = R.m;
+  PBR_TRY(lz_ritz(c, R, m, R.beta[m - 1], o));
+  if (R.nconv >= R.nev || R.restarts >= o.maxit_outer) {
+    R.done = true;
+    return ST_OK;
+  }
+  int kk = R.nev + (m - R.nev) / 2;
+  if (kk >= m) kk = m - 1;
+  std::vector<zc> Yk((size_t)m * kk);
+  for (int cc = 0; cc < kk; ++cc)
+    for (int r = 0; r < m; ++r) {
+      const int col = R.order[cc];
+      Yk[(size_t)cc * m + r] =
+          zc(R.Yr[2 * ((size_t)col * m + r)], R.Yr[2 * ((size_t)col * m + r) + 1]);
+    }
+  PBR_TRY(upload_small(c, W.small, Yk));
+  PBR_TRY(combine(c, SO, n3, m, kk, W.U, ld, W.small, W.U2, ld));
+  PBR_TRY(vec_copy(c, SO, n3, W.U + (long)m * ld, W.U2 + (long)kk * ld));
+  std::swap(W.U, W.U2);
+  std::fill(R.H.begin(), R.H.end(), zc(0, 0));
+  for (int i = 0; i < kk; ++i) R.H[(size_t)i * ldh + i] = R.theta[R.order[i]];
+  R.j = kk;
+  ++R.restarts;
+  return ST_OK;
+}
+
+// Ritz vectors of the nev largest mu, final Rayleigh quotients and residuals
+// with the exact operator, eigenvalues ascending.
+int lz_finish(pbr_ctx* c, LanczosRun& R, const double kappa[3], double* evals, cplx* evecs_dev,
+              pbr_stats* st) {
+  LayoutWork& W = c->work[R.block + 1];
+  DevMaterial& M = c->material(R.block);
+  const hipStream_t SO = c->stream;
+  const long N = R.N, n3 = R.n3, ld = R.ld;
+  const int m = R.m;
+  const int nout = std::min(R.nev, m);
   std::vector<zc> Yk((size_t)m * nout);
   for (int cc = 0; cc < nout; ++cc)
     for (int r = 0; r < m; ++r) {
-      const int col = order[cc];
-      Yk[(size_t)cc * m + r] = zc(Yr[2 * ((size_t)col * m + r)], Yr[2 * ((size_t)col * m + r) + 1]);
+      const int col = R.order[cc];
+      Yk[(size_t)cc * m + r] =
+          zc(R.Yr[2 * ((size_t)col * m + r)], R.Yr[2 * ((size_t)col * m + r) + 1]);
     }
-  PBR_TRY(upload_small(c, W, W.small, Yk));
+  PBR_TRY(upload_small(c, W.small, Yk));
   PBR_TRY(combine(c, SO, n3, m, nout, W.U, ld, W.small, W.U2, ld));
-  // final Rayleigh quotients and residuals with the exact operator
-  const Geo g = make_geo(c, block, kappa);
+  const Geo g = make_geo(c, R.block, kappa);
   std::vector<std::pair<double, int>> lam(nout);
   double max_res = 0.0;
   for (int i = 0; i < nout; ++i) {
     cplx* u = W.U2 + (long)i * ld;
-    if (gamma) PBR_TRY(project_null(c, W, u));
+    if (R.gamma) PBR_TRY(project_null(c, W, u));
     // v = M^{-1/2} u  -> W.t ;  y = A v -> W.q
     PBR_TRY(vec_diag_scale(c, SO, N, M.isrho, u, W.t));
-    PBR_TRY(launch_apply(c, g, block, 0.0, W.t, W.q));
-    cnt.matvecs += 1;
+    PBR_TRY(launch_apply(c, g, R.block, 0.0, W.t, W.q));
+    R.cnt.matvecs += 1;
     double vals[3];
     PBR_TRY(dot_real_async(c, SO, n3, W.t, W.q, W.part, W.dscal));       // v^H A v
     PBR_TRY(dot_real_async(c, SO, n3, u, u, W.part, W.dscal + 1));        // v^H M v
     PBR_TRY(dot_real_async(c, SO, n3, W.q, W.q, W.part, W.dscal + 2));    // |Av|^2
-    PBR_TRY(readback(c, W, W.dscal, vals, 3));
+    PBR_TRY(readback(c, W.dscal, vals, 3));
     const double l = vals[0] / vals[1];
     // r = A v - l M v = y - l * srho .* u
     PBR_TRY(vec_resid(c, SO, N, l, M.srho, u, W.q, W.z));
     double rr;
     PBR_TRY(dot_real_async(c, SO, n3, W.z, W.z, W.part, W.dscal));
-    PBR_TRY(readback(c, W, W.dscal, &rr, 1));
+    PBR_TRY(readback(c, W.dscal, &rr, 1));
     // |M v| = |srho .* u|
     PBR_TRY(vec_diag_scale(c, SO, N, M.srho, u, W.z));
     double mv;
     PBR_TRY(dot_real_async(c, SO, n3, W.z, W.z, W.part, W.dscal));
-    PBR_TRY(readback(c, W, W.dscal, &mv, 1));
+    PBR_TRY(readback(c, W.dscal, &mv, 1));
     const double denom = std::sqrt(vals[2]) + std::fabs(l) * std::sqrt(mv);
     const double rel = denom > 0 ? std::sqrt(rr) / denom : 0.0;
     max_res = std::max(max_res, rel);
@@ -525,36 +597,91 @@ int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double s
   }
   PBR_HIP(c, hipStreamSynchronize(SO));
   if (st) {
-    st->outer_iters += restarts;
-    st->op_applies += cnt.applies;
-    st->pcg_iters_total += cnt.pcg_total;
-    st->pcg_iters_max = std::max(st->pcg_iters_max, cnt.pcg_max);
-    st->matvecs += cnt.matvecs;
-    st->n_zero += n_zero;
-    st->converged += std::min(nconv, nev);
+    st->outer_iters += R.restarts;
+    st->op_applies += R.cnt.applies;
+    st->pcg_iters_total += R.cnt.pcg_total;
+    st->pcg_iters_max = std::max(st->pcg_iters_max, R.cnt.pcg_max);
+    st->matvecs += R.cnt.matvecs;
+    st->n_zero += R.n_zero;
+    st->converged += std::min(R.nconv, R.nev);
     st->pcg_avg = st->op_applies ? (double)st->pcg_iters_total / st->op_applies : 0.0;
     st->max_rel_resid = std::max(st->max_rel_resid, max_res);
-    st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st->seconds +=
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t0).count();
   }
-  if (nconv < nev && !exhausted) {
+  if (R.nconv < R.nev && !R.exhausted) {
     c->set_error("outer Krylov iteration did not converge within maxit_outer restarts");
     return ST_ENOCONV;
   }
   return ST_OK;
 }
 
-namespace {
-
-// Streams and events of the concurrent block solves (created once per context).
-int ensure_block_streams(pbr_ctx* c) {
-  for (int b = 0; b < 4; ++b) {
-    if (!c->bstream[b]) PBR_HIP(c, hipStreamCreateWithFlags(&c->bstream[b], hipStreamNonBlocking));
-    if (!c->join_ev[b])
-      PBR_HIP(c, hipEventCreateWithFlags(&c->join_ev[b], hipEventDisableTiming));
+// One shift-invert application w = M^{1/2} (A + shift M)^{-1} M^{1/2} u_j for
+// every active run, as one batched PCG.
+int op_apply_batch(pbr_ctx* c, const double kappa[3], double shift, const pbr_opts& o,
+                   LanczosRun* const* R, int na) {
+  int blocks[PBR_MAX_BATCH], its[PBR_MAX_BATCH], conv[PBR_MAX_BATCH];
+  const cplx* b[PBR_MAX_BATCH];
+  cplx* x[PBR_MAX_BATCH];
+  for (int t = 0; t < na; ++t) {
+    LayoutWork& W = c->work[R[t]->block + 1];
+    const DevMaterial& M = c->material(R[t]->block);
+    blocks[t] = R[t]->block;
+    PBR_TRY(vec_diag_scale(c, c->stream, W.N, M.srho, W.U + (long)R[t]->j * R[t]->ld, W.b));
+    b[t] = W.b;
+    x[t] = W.t;
   }
-  if (!c->fork_ev) PBR_HIP(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  const int s = pcg_solve_batch(c, na, blocks, kappa, shift, b, x, o, its, conv);
+  if (s != ST_OK && s != ST_ENOCONV) return s;
+  for (int t = 0; t < na; ++t) {
+    LayoutWork& W = c->work[R[t]->block + 1];
+    const DevMaterial& M = c->material(R[t]->block);
+    OpCounters& k = R[t]->cnt;
+    k.applies += 1;
+    k.pcg_total += its[t];
+    k.pcg_max = std::max(k.pcg_max, its[t]);
+    k.matvecs += its[t];
+    if (!conv[t]) k.pcg_fail += 1;
+    PBR_TRY(vec_diag_scale(c, c->stream, W.N, M.srho, W.t, W.w));
+  }
   return ST_OK;
 }
+
+}  // namespace
+
+// Lanczos runs for nb layouts of one kind in lockstep (one batched PCG per
+// step).  Per-layout results go to evals[t], evecs_dev[t] (may be null) and
+// st[t]; rc[t] is each run's status.  Returns the first hard error, else OK.
+int lanczos_batch(pbr_ctx* c, const double kappa[3], int nb, const int* blocks, const int* nev,
+                  double shift, const pbr_opts& o, double* const* evals,
+                  cplx* const* evecs_dev, pbr_stats* st, int* rc) {
+  LanczosRun R[PBR_MAX_BATCH];
+  for (int t = 0; t < nb; ++t) PBR_TRY(lz_start(c, R[t], blocks[t], nev[t], kappa, o));
+  for (;;) {
+    LanczosRun* act[PBR_MAX_BATCH];
+    int na = 0;
+    for (int t = 0; t < nb; ++t)
+      if (!R[t].done) act[na++] = &R[t];
+    if (!na) break;
+    PBR_TRY(op_apply_batch(c, kappa, shift, o, act, na));
+    for (int t = 0; t < na; ++t) PBR_TRY(lz_step(c, *act[t], o));
+  }
+  for (int t = 0; t < nb; ++t) {
+    rc[t] = lz_finish(c, R[t], kappa, evals[t], evecs_dev ? evecs_dev[t] : nullptr,
+                      st ? &st[t] : nullptr);
+    if (rc[t] != ST_OK && rc[t] != ST_ENOCONV) return rc[t];
+  }
+  return ST_OK;
+}
+
+int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double shift,
+                 const pbr_opts& o, double* evals, cplx* evecs_dev, pbr_stats* st) {
+  int rc = ST_OK;
+  PBR_TRY(lanczos_batch(c, kappa, 1, &block, &nev, shift, o, &evals, &evecs_dev, st, &rc));
+  return rc;
+}
+
+namespace {
 
 void add_stats(pbr_stats* acc, const pbr_stats& one) {
   acc->outer_iters += one.outer_iters;
@@ -568,59 +695,35 @@ void add_stats(pbr_stats* acc, const pbr_stats& one) {
   acc->pcg_avg = acc->op_applies ? (double)acc->pcg_iters_total / acc->op_applies : 0.0;
 }
 
-// Solve the blocks in `mask` concurrently: one host thread and one stream per
-// block (the blocks share nothing but the read-only context data).  The block
-// streams are ordered after everything already queued on the context stream, and
-// the context stream after them on return.
+// Solve the blocks in `mask`: all in lockstep (one batched PCG per step), or
+// one after another with opts.concurrent = 0.
 int solve_blocks(pbr_ctx* c, const double kappa[3], int mask, const int nev_b[4], double shift,
                  const pbr_opts& o, std::vector<double>* vals, pbr_stats* st) {
-  if (!o.concurrent) {
-    int status = ST_OK;
-    for (int b = 0; b < 4; ++b) {
-      if (!(mask & (1 << b))) continue;
-      vals[b].assign(nev_b[b], 0.0);
-      pbr_stats one;
-      std::memset(&one, 0, sizeof(one));
-      const int s = lanczos_eigs(c, kappa, b, nev_b[b], shift, o, vals[b].data(), nullptr, &one);
-      if (s != ST_OK && s != ST_ENOCONV) return s;
-      if (s == ST_ENOCONV) status = ST_ENOCONV;
-      if (st) add_stats(st, one);
-    }
-    return status;
-  }
-  PBR_TRY(ensure_block_streams(c));
-  for (int b = 0; b < 4; ++b)
-    if (mask & (1 << b)) PBR_TRY(ensure_work(c, b));
-  PBR_HIP(c, hipEventRecord(c->fork_ev, c->stream));
-  int rc[4] = {ST_OK, ST_OK, ST_OK, ST_OK};
+  int blocks[4], nev[4], rc[4];
+  double* ev[4];
   pbr_stats part[4];
   std::memset(part, 0, sizeof(part));
-  std::vector<std::thread> th;
+  int nb = 0;
   for (int b = 0; b < 4; ++b) {
     if (!(mask & (1 << b))) continue;
     vals[b].assign(nev_b[b], 0.0);
-    th.emplace_back([&, b]() {
-      if (hipSetDevice(c->device) != hipSuccess ||
-          hipStreamWaitEvent(c->bstream[b], c->fork_ev, 0) != hipSuccess) {
-        c->set_error("could not start a block solve on its stream");
-        rc[b] = ST_EDEVICE;
-        return;
-      }
-      c->work[b + 1].stream = c->bstream[b];
-      rc[b] = lanczos_eigs(c, kappa, b, nev_b[b], shift, o, vals[b].data(), nullptr, &part[b]);
-      if (hipEventRecord(c->join_ev[b], c->bstream[b]) != hipSuccess) rc[b] = ST_EDEVICE;
-      c->work[b + 1].stream = nullptr;
-    });
+    blocks[nb] = b;
+    nev[nb] = nev_b[b];
+    ev[nb] = vals[b].data();
+    rc[nb] = ST_OK;
+    ++nb;
   }
-  for (auto& t : th) t.join();
-  for (int b = 0; b < 4; ++b)
-    if (mask & (1 << b)) PBR_HIP(c, hipStreamWaitEvent(c->stream, c->join_ev[b], 0));
+  if (o.concurrent) {
+    PBR_TRY(lanczos_batch(c, kappa, nb, blocks, nev, shift, o, ev, nullptr, part, rc));
+  } else {
+    for (int t = 0; t < nb; ++t)
+      PBR_TRY(lanczos_batch(c, kappa, 1, blocks + t, nev + t, shift, o, ev + t, nullptr,
+                            part + t, rc + t));
+  }
   int status = ST_OK;
-  for (int b = 0; b < 4; ++b) {
-    if (!(mask & (1 << b))) continue;
-    if (st) add_stats(st, part[b]);
-    if (rc[b] == ST_ENOCONV && status == ST_OK) status = ST_ENOCONV;
-    if (rc[b] != ST_OK && rc[b] != ST_ENOCONV) status = rc[b];
+  for (int t = 0; t < nb; ++t) {
+    if (st) add_stats(st, part[t]);
+    if (rc[t] == ST_ENOCONV) status = ST_ENOCONV;
   }
   return status;
 }

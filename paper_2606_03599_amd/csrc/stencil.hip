@@ -40,17 +40,25 @@
 
 namespace {
 
-struct ApplyArgs {
-  Geo g;
-  int N;              // nodes of the layout (all offsets below fit in 32 bits)
-  double s;
-  int tiles_i, tiles_j, chunk;
+// One layout of a batched launch (the parity blocks of one grid share the box
+// shape and differ in their class bits, material and vectors).
+struct ApplyBlock {
   const cplx* x;
   cplx* y;
   const double* C;
   const double* rho;
-  const PcgScalars* st;  // optional: the launch does nothing once st->done != 0
-  double* part;           // optional: per-work-group partials of Re(x^H y)
+  const PcgScalars* st;  // optional: this block's work-groups return once st->done != 0
+  double* part;          // optional: per-work-group partials of Re(x^H y)
+  int a, c;              // class bits of the block (unused in the natural layout)
+};
+
+struct ApplyArgs {
+  Geo g;
+  int N;              // nodes of one layout (all offsets below fit in 32 bits)
+  double s;
+  int tiles_i, tiles_j, chunk;
+  int per;            // work-groups per layout
+  ApplyBlock b[PBR_MAX_BATCH];
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -197,26 +205,32 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   __shared__ cplx tau_s[6 * NP];
   __shared__ cplx x_s[4][3 * NX];
   __shared__ double red[NT / 64 + 1];
-  if (A.st && A.st->done) return;  // whole work-group
-  const Geo& g = A.g;
-  const int L1 = g.L1, L2 = g.L2, L3 = g.L3;
-  const int N = A.N;
-  const __amdgpu_buffer_rsrc_t rx = rsrc(A.x, (unsigned)N * 48u);
-  const __amdgpu_buffer_rsrc_t ry = rsrc(A.y, (unsigned)N * 48u);
-  const __amdgpu_buffer_rsrc_t rc = rsrc(A.C, (unsigned)N * 168u);
-  const __amdgpu_buffer_rsrc_t rr = rsrc(A.rho, (unsigned)N * 8u);
-  const int cs = N * 16, ds = N * 8;
 
   // XCD-aware numbering: work-groups are dealt round-robin over 8 XCDs, so
-  // give each XCD a contiguous range of (tile, chunk) indices.
+  // give each XCD a contiguous range of (layout, tile, chunk) indices.
   const int W = gridDim.x;
   const int w = blockIdx.x;
-  const int per = W / 8, rem = W % 8;
+  const int per8 = W / 8, rem = W % 8;
   const int xcd = w % 8, slot = w / 8;
-  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+  const int logical =
+      (xcd < rem ? xcd * (per8 + 1) : rem * (per8 + 1) + (xcd - rem) * per8) + slot;
+  const int blk = logical / A.per;
+  const int local = logical - blk * A.per;
+  const ApplyBlock& P = A.b[blk];
+  if (P.st && P.st->done) return;  // whole work-group
+  Geo g = A.g;
+  g.a = P.a;
+  g.c = P.c;
+  const int L1 = g.L1, L2 = g.L2, L3 = g.L3;
+  const int N = A.N;
+  const __amdgpu_buffer_rsrc_t rx = rsrc(P.x, (unsigned)N * 48u);
+  const __amdgpu_buffer_rsrc_t ry = rsrc(P.y, (unsigned)N * 48u);
+  const __amdgpu_buffer_rsrc_t rc = rsrc(P.C, (unsigned)N * 168u);
+  const __amdgpu_buffer_rsrc_t rr = rsrc(P.rho, (unsigned)N * 8u);
+  const int cs = N * 16, ds = N * 8;
   const int ntile = A.tiles_i * A.tiles_j;
-  const int tile = logical % ntile;
-  const int chunk = logical / ntile;
+  const int tile = local % ntile;
+  const int chunk = local / ntile;
   const int i0 = (tile % A.tiles_i) * TI;
   const int j0 = (tile / A.tiles_i) * TJ;
   const int k0 = chunk * A.chunk;
@@ -436,9 +450,9 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
     need_cur = need_nxt;
     __syncthreads();
   }
-  if (A.part) {
+  if (P.part) {
     const double v = block_sum_all(xy, red);
-    if (tid == 0) A.part[blockIdx.x] = v;
+    if (tid == 0) P.part[local] = v;
   }
 }
 
@@ -446,41 +460,63 @@ constexpr int TILE_I = 16, TILE_J = 16;
 
 }  // namespace
 
-int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
-                 PcgScalars* st, double* part, long part_cap, int* nparts) {
-  DevMaterial& M = c->material(block);
-  if (M.N * 168L >= (1L << 31)) {
+int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,
+                       long part_cap, int* nparts) {
+  if (nb < 1 || nb > PBR_MAX_BATCH) {
+    c->set_error("batch of 1 to 4 layouts expected");
+    return ST_EINVAL;
+  }
+  const long Nl = c->layout_nodes(g.blocked ? 0 : -1);
+  if (Nl * 168L >= (1L << 31)) {
     c->set_error("grid too large for 32-bit buffer offsets of the stencil kernel");
     return ST_EINVAL;
   }
   ApplyArgs A;
   A.g = g;
-  A.N = (int)M.N;
+  A.N = (int)Nl;
   A.s = s;
-  A.x = x;
-  A.y = y;
-  A.C = M.C;
-  A.rho = M.rho;
-  A.st = st;
-  A.part = part;
   A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
   A.tiles_j = (g.L2 + TILE_J - 1) / TILE_J;
-  // chunk length: about one work-group per CU (256 CUs); longer chunks amortise
-  // the two partial planes a chunk stages at its ends
+  // chunk length: about one work-group per CU (256 CUs) for one layout; longer
+  // chunks amortise the two partial planes a chunk stages at its ends
   const long tiles = (long)A.tiles_i * A.tiles_j;
   int chunk = (int)std::max<long>(1, (tiles * g.L3) / 256);
   chunk = std::max(chunk, 4);
   chunk = std::min(chunk, g.L3);
   A.chunk = chunk;
   const int nchunks = (g.L3 + chunk - 1) / chunk;
-  const unsigned grid = (unsigned)(tiles * nchunks);
-  if (nparts) *nparts = (int)grid;
-  if (part && (long)grid > part_cap) {
-    c->set_error("grid too large for the PCG partial buffers");
-    return ST_EINVAL;
+  A.per = (int)(tiles * nchunks);
+  if (nparts) *nparts = A.per;
+  for (int t = 0; t < nb; ++t) {
+    const DevMaterial& M = c->material(L[t].block);
+    ApplyBlock& B = A.b[t];
+    B.x = L[t].x;
+    B.y = L[t].y;
+    B.C = M.C;
+    B.rho = M.rho;
+    B.st = L[t].st;
+    B.part = L[t].part;
+    B.a = L[t].block >= 0 ? L[t].block >> 1 : 0;
+    B.c = L[t].block >= 0 ? L[t].block & 1 : 0;
+    if (B.part && A.per > part_cap) {
+      c->set_error("grid too large for the PCG partial buffers");
+      return ST_EINVAL;
+    }
   }
+  const unsigned grid = (unsigned)((long)A.per * nb);
   hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
-                     dim3(TILE_I * TILE_J + 64), 0, c->stream_of(block), A);
+                     dim3(TILE_I * TILE_J + 64), 0, c->stream, A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
+}
+
+int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
+                 PcgScalars* st, double* part, long part_cap, int* nparts) {
+  ApplyLayout L;
+  L.block = block;
+  L.x = x;
+  L.y = y;
+  L.st = st;
+  L.part = part;
+  return launch_apply_batch(c, g, 1, &L, s, part_cap, nparts);
 }
