@@ -146,6 +146,15 @@ pbr_status pbr_block_scatter(pbr_ctx *c, int block, const void *blk, void *full,
 pbr_status pbr_apply(pbr_ctx *c, const double kappa[3], int block, double s,
                      const void *x, void *y, int on_device);
 
+/* y_b = (A_sigma(b) + s M_sigma(b)) x_b for all four parity blocks in one
+ * launch: the block-diagonal form of A_h(k) + s M_h in the parity-block basis
+ * (Theorem 4.1, Corollary 4.2).  x and y hold the four block vectors back to
+ * back, block 0 first, each 3n/4 complex in the block layout of CONVENTIONS
+ * (3n complex in all).  Even grids only (PBR_EODDGRID otherwise); x and y must
+ * not overlap. */
+pbr_status pbr_apply_blocks(pbr_ctx *c, const double kappa[3], double s, const void *x,
+                            void *y, int on_device);
+
 /* z = T_xi diag_m(K(m)^-1) T_xi^H r with K(m) = Bhat(m) C_ref Bhat(m)^H +
  * shift * rho_ref * I_3: the FFT-diagonal preconditioner of the shifted system
  * (Fourier bases of Sec. 5.1-5.2, symbols Eqs. 5.8-5.11; T_xi = T full,

@@ -364,6 +364,34 @@ pbr_status pbr_block_scatter(pbr_ctx* c, int block, const void* blk, void* full,
   return (pbr_status)stage_out(c, f, full, 3 * c->n, on_device);
 }
 
+pbr_status pbr_apply_blocks(pbr_ctx* c, const double kappa[3], double s, const void* x,
+                            void* y, int on_device) {
+  if (!c) return PBR_EINVAL;
+  int st = check_block(c, 0);
+  if (st == ST_OK) st = check_kappa(c, kappa);
+  if (st == ST_OK && (!x || !y || !std::isfinite(s))) {
+    c->set_error("x, y must be non-NULL and s finite");
+    st = ST_EINVAL;
+  }
+  if (st == ST_OK) st = check_material(c);
+  if (st != ST_OK) return (pbr_status)st;
+  hipSetDevice(c->device);
+  const long nb3 = 3 * c->layout_nodes(0);
+  Staged sx, sy;
+  if ((st = stage_in(c, x, 4 * nb3, on_device, sx)) != ST_OK) return (pbr_status)st;
+  if ((st = stage_in(c, nullptr, 4 * nb3, on_device, sy)) != ST_OK) return (pbr_status)st;
+  if (on_device) sy.dev = (cplx*)y;
+  const Geo g = make_geo(c, 0, kappa);
+  ApplyLayout L[4];
+  for (int b = 0; b < 4; ++b) {
+    L[b].block = b;
+    L[b].x = sx.dev + b * nb3;
+    L[b].y = sy.dev + b * nb3;
+  }
+  if ((st = launch_apply_batch(c, g, 4, L, s)) != ST_OK) return (pbr_status)st;
+  return (pbr_status)stage_out(c, sy, y, 4 * nb3, on_device);
+}
+
 pbr_status pbr_apply(pbr_ctx* c, const double kappa[3], int block, double s, const void* x,
                      void* y, int on_device) {
   if (!c) return PBR_EINVAL;

@@ -15,8 +15,9 @@
 //  * a work-group owns a TI x TJ tile of the (i, j) plane of the layout box and
 //    streams through a chunk of planes k in [k0, k1);
 //  * the velocity is staged in LDS once per plane for the tile and the ring its
-//    backward neighbours reach, in a ring of four planes (three read, the
-//    next one written from registers loaded a whole step earlier).  Staging
+//    backward neighbours reach, in a rolling window of three planes (the
+//    loads of the next plane are issued first in a step, ahead of the stiffness
+//    prefetch, and stored at its end).  Staging
 //    multiplies every value by the Bloch phase of its (possibly out-of-box)
 //    position, i.e. it stores the extended field v(x + n_l e_l) = e^{i phi_l} v(x)
 //    of Eq. 3.2, so no later step needs wrap or phase logic;
@@ -189,7 +190,7 @@ __device__ inline void contrib(const Geo& g, const cplx* lds, int p, int d, cplx
   out[2] = cfma(c2, t2, cfma(c1, t3, cscale(c0, t4)));
 }
 
-__device__ inline int wslot(int v) { return v & 3; }  // v mod 4, also for v < 0
+__device__ inline int wslot(int v) { return ((v % 3) + 3) % 3; }
 
 // Work-group layout: TI*TJ "own" lanes (one output column each) followed by one
 // wave of ring lanes (the i+1 column and the j-1 / j+TJ rows of the tile).
@@ -203,7 +204,7 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   constexpr int XPASS = (NX + NT - 1) / NT;
   static_assert(NH <= 64, "tau ring must fit in one wave");
   __shared__ cplx tau_s[6 * NP];
-  __shared__ cplx x_s[4][3 * NX];
+  __shared__ cplx x_s[3][3 * NX];
   __shared__ double red[NT / 64 + 1];
 
   // XCD-aware numbering: work-groups are dealt round-robin over 8 XCDs, so
@@ -347,8 +348,7 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   }
   // velocity plane s+2 is stored at the top of step s from registers loaded one
   // step earlier, so its loads have a whole step to arrive
-  cplx xq[XPASS][3];
-  if (k0 + 1 <= k1 + 1) stage_load(k0 + 1, xq);
+
   bool need_cur = needed_at(k0 - 1);
   double Ccur[21], rcur;
   load_C(k0 - 1, need_cur, Ccur, rcur);
@@ -357,8 +357,9 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   for (int s = k0 - 1; s <= k1; ++s) {
     // issue the loads of the next stiffness plane and of velocity plane s+2
     // ring slots: s-1, s, s+1 are read below; s+2 goes into the slot of s-2
-    if (s + 2 <= k1 + 1) stage_store(s + 2, xq);
-    if (s + 3 <= k1 + 1) stage_load(s + 3, xq);
+    cplx xnext[XPASS][3];
+    const bool more_x = s + 2 <= k1 + 1;
+    if (more_x) stage_load(s + 2, xnext);
     const bool need_nxt = (s + 1 <= k1) && needed_at(s + 1);
     double Cnxt[21], rnxt;
     load_C(s + 1, need_nxt, Cnxt, rnxt);
@@ -437,6 +438,7 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
         }
       }
     }
+    if (more_x) stage_store(s + 2, xnext);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       A0[a] = A1[a];

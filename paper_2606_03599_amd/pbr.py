@@ -72,6 +72,7 @@ _SIGS = {
     "pbr_block_scatter": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]),
     "pbr_apply": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
                                  ctypes.c_int]),
+    "pbr_apply_blocks": (ctypes.c_int, [_vp, _dp, ctypes.c_double, _vp, _vp, ctypes.c_int]),
     "pbr_precond": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
                                    ctypes.c_int]),
     "pbr_solve": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
@@ -218,6 +219,14 @@ def pbr_apply(ctx, kappa, block, s, x, y):
     return ky
 
 
+def pbr_apply_blocks(ctx, kappa, s, x, y):
+    kp, kk = _kappa(kappa)
+    px, ox, kx = _vec(x)
+    py, oy, ky = _vec(y)
+    _check(ctx, lib().pbr_apply_blocks(ctx, kp, float(s), px, py, _same_place(ox, oy)))
+    return ky
+
+
 def pbr_precond(ctx, kappa, block, shift, r, z):
     kp, kk = _kappa(kappa)
     pr, orr, kr = _vec(r)
@@ -341,6 +350,9 @@ class Context:
 
     def apply(self, kappa, block, s, x, y):
         return pbr_apply(self.h, kappa, block, s, x, y)
+
+    def apply_blocks(self, kappa, s, x, y):
+        return pbr_apply_blocks(self.h, kappa, s, x, y)
 
     def precond(self, kappa, block, shift, r, z):
         return pbr_precond(self.h, kappa, block, shift, r, z)

@@ -48,6 +48,42 @@ def test_apply_small_full_and_blocks(dims, A_lat):
     ctx.close()
 
 
+@pytest.mark.parametrize("dims", [(2, 2, 2), (8, 8, 8), (4, 6, 2), (6, 4, 10)])
+def test_apply_blocks_batched(dims):
+    """All four blocks in one launch (pbr_apply_blocks) vs the oracle's block
+    operators, and bit-identical to four single-block launches."""
+    log(f"apply_blocks dims={dims}")
+    C21, rho = random_spd_field(dims, seed=7)
+    n = int(np.prod(dims))
+    ctx = make_ctx(dims, C21, rho)
+    kap, s = (0.35, -0.2, 0.15), 0.45
+    A = D.assemble_A(dims, kap, C21)
+    M = D.assemble_M(rho)
+    x = complex_gaussian(3 * n, seed=12345)
+    xs = [Bk.gather(x, dims, b) for b in range(4)]
+    y = to_host(ctx.apply_blocks(kap, s, to_dev(np.concatenate(xs)),
+                                 to_dev(np.zeros(3 * n, complex))))
+    nb3 = 3 * n // 4
+    for b in range(4):
+        Ab = Bk.block_operator(A, dims, b)
+        Mb = Bk.block_operator(M, dims, b)
+        yb_or = Ab @ xs[b] + s * (Mb @ xs[b])
+        assert rel(y[b * nb3:(b + 1) * nb3], yb_or) <= TOL, b
+        yb = to_host(ctx.apply(kap, b, s, to_dev(xs[b]), to_dev(np.zeros(nb3, complex))))
+        assert np.array_equal(yb, y[b * nb3:(b + 1) * nb3]), b
+    ctx.close()
+
+
+def test_apply_blocks_rejects_odd_grid():
+    C21, rho = random_spd_field((3, 4, 4), seed=1)
+    ctx = make_ctx((3, 4, 4), C21, rho)
+    from paper_2606_03599_amd import pbr
+    with pytest.raises(pbr.PbrError) as e:
+        ctx.apply_blocks(KAPPA, 0.0, to_dev(np.zeros(144, complex)), to_dev(np.zeros(144, complex)))
+    assert e.value.status == pbr.PBR_EODDGRID
+    ctx.close()
+
+
 @pytest.mark.parametrize("dims", [(3, 3, 3), (1, 2, 3), (5, 4, 2)])
 def test_apply_odd_full_space(dims):
     log(f"apply odd dims={dims}")
