@@ -19,6 +19,9 @@ eigen           dense generalized eigenvalues, Gamma-point null space and the
 fourier         Bloch Fourier bases T, F_sigma, T_sigma, symbols and the
                 FFT-diagonal preconditioner (Sec. 5, Appendix B)
 solve           direct solution of the shifted system (Eq. 6.2)
+gradient        Hellmann-Feynman derivatives of eigenvalues with respect to the
+                nodewise stiffness and density (first-order perturbation of the
+                pencil of Eq. 3.15)
 continuum       textbook Christoffel equation, used only as a pin
 
 Parity status: every function is pinned by tests under ``tests/`` against
