@@ -200,6 +200,23 @@ pbr_status pbr_band_path(pbr_ctx *c, int nk, const double *kappas, int nev,
                          int blocked, double shift, const pbr_opts *opts,
                          double *evals, pbr_stats *st);
 
+/* Derivatives of eigenvalues with respect to the material (first-order
+ * perturbation of the pencil of Eq. 3.15): for nvec eigenpairs (lambda[s], v_s)
+ * of layout `block` at kappa, with v_s^H M v_s = 1 as pbr_eigs returns them,
+ * ADDS sum_s weight[s] * d lambda_s / d C21 to gC21 (n x 21, natural order and
+ * the C21 entry order of CONVENTIONS) and sum_s weight[s] * d lambda_s / d rho
+ * to grho (n):
+ *   d lambda / d C21_(a,b)(x) = |e_a(x)|^2 (a = b), 2 Re(conj(e_a) e_b) (a < b),
+ *   d lambda / d rho(x) = -lambda |v(x)|^2,
+ * with the strains e = B_h^H v recomputed from v.  A single derivative is
+ * defined for a simple eigenvalue; for a cluster of equal eigenvalues pass an
+ * orthonormal basis of the cluster with equal weights (the sum is defined).
+ * evecs: nvec vectors of pbr_block_dim(c, block) complex, one after another;
+ * lambda, weight: host arrays.  Block derivatives vanish off the block's nodes. */
+pbr_status pbr_eig_grad(pbr_ctx *c, const double kappa[3], int block, int nvec,
+                        const double *lambda, const double *weight, const void *evecs,
+                        int evecs_on_device, double *gC21, double *grho, int grad_on_device);
+
 /* Message of the last failing call on c (or of the last failing pbr_create when
  * c is NULL).  The string lives until the next call on c. */
 const char *pbr_last_error(const pbr_ctx *c);

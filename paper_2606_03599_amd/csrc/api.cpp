@@ -364,6 +364,66 @@ pbr_status pbr_block_scatter(pbr_ctx* c, int block, const void* blk, void* full,
   return (pbr_status)stage_out(c, f, full, 3 * c->n, on_device);
 }
 
+pbr_status pbr_eig_grad(pbr_ctx* c, const double kappa[3], int block, int nvec,
+                        const double* lambda, const double* weight, const void* evecs,
+                        int evecs_on_device, double* gC21, double* grho, int grad_on_device) {
+  if (!c) return PBR_EINVAL;
+  int st = check_block(c, block);
+  if (st == ST_OK) st = check_kappa(c, kappa);
+  if (st == ST_OK && (nvec < 1 || !lambda || !weight || !evecs || !gC21 || !grho)) {
+    c->set_error("nvec >= 1 and non-NULL lambda, weight, evecs, gC21, grho required");
+    st = ST_EINVAL;
+  }
+  if (st == ST_OK) st = check_material(c);
+  if (st != ST_OK) return (pbr_status)st;
+  hipSetDevice(c->device);
+  const long n3 = 3 * c->layout_nodes(block);
+  Staged sv;
+  if ((st = stage_in(c, evecs, n3 * nvec, evecs_on_device, sv)) != ST_OK) return (pbr_status)st;
+  double* dC = grad_on_device ? gC21 : nullptr;  // dev_alloc fills null pointers only
+  double* dr = grad_on_device ? grho : nullptr;
+  const size_t bC = sizeof(double) * 21 * (size_t)c->n, br = sizeof(double) * (size_t)c->n;
+  if (!grad_on_device) {
+    if ((st = dev_alloc(c, (void**)&dC, bC)) != ST_OK) return (pbr_status)st;
+    if ((st = dev_alloc(c, (void**)&dr, br)) != ST_OK) {
+      dev_free(dC);
+      return (pbr_status)st;
+    }
+  }
+  hipError_t he = hipSuccess;
+  auto fail = [&](const char* msg) {
+    c->set_error(std::string(msg) + ": " + hipGetErrorString(he));
+    if (!grad_on_device) {
+      dev_free(dC);
+      dev_free(dr);
+    }
+    return PBR_EDEVICE;
+  };
+  if (!grad_on_device &&
+      ((he = hipMemcpyAsync(dC, gC21, bC, hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+       (he = hipMemcpyAsync(dr, grho, br, hipMemcpyHostToDevice, c->stream)) != hipSuccess))
+    return fail("copying the gradient fields to the device failed");
+  const Geo g = make_geo(c, block, kappa);
+  if ((st = launch_eig_grad(c, g, block, nvec, lambda, weight, sv.dev, dC, dr)) != ST_OK) {
+    if (!grad_on_device) {
+      dev_free(dC);
+      dev_free(dr);
+    }
+    return (pbr_status)st;
+  }
+  if (!grad_on_device) {
+    if ((he = hipMemcpyAsync(gC21, dC, bC, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (he = hipMemcpyAsync(grho, dr, br, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (he = hipStreamSynchronize(c->stream)) != hipSuccess)
+      return fail("copying the gradient fields to the host failed");
+    dev_free(dC);
+    dev_free(dr);
+  } else if (!evecs_on_device) {
+    if ((he = hipStreamSynchronize(c->stream)) != hipSuccess) return fail("gradient launch failed");
+  }
+  return PBR_OK;
+}
+
 pbr_status pbr_apply_blocks(pbr_ctx* c, const double kappa[3], double s, const void* x,
                             void* y, int on_device) {
   if (!c) return PBR_EINVAL;

@@ -146,6 +146,11 @@ int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
 int launch_pcg_precond_batch(pbr_ctx* c, const double kappa[3], int nb, const PcgStep* P,
                              double shift);
 
+// Adds sum_s w[s] d lambda_s / d (C21, rho) of nvec M-normalised eigenvectors v
+// (vector-major, layout `block`) to the natural-order fields gC (n x 21), grho.
+int launch_eig_grad(pbr_ctx* c, const Geo& g, int block, int nvec, const double* lam,
+                    const double* w, const cplx* v, double* gC, double* grho);
+
 // solver drivers (solver.cpp)
 int ensure_work(pbr_ctx* c, int block);
 int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b, cplx* x,

@@ -73,6 +73,8 @@ _SIGS = {
     "pbr_apply": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
                                  ctypes.c_int]),
     "pbr_apply_blocks": (ctypes.c_int, [_vp, _dp, ctypes.c_double, _vp, _vp, ctypes.c_int]),
+    "pbr_eig_grad": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _vp,
+                                    ctypes.c_int, _vp, _vp, ctypes.c_int]),
     "pbr_precond": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
                                    ctypes.c_int]),
     "pbr_solve": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
@@ -227,6 +229,22 @@ def pbr_apply_blocks(ctx, kappa, s, x, y):
     return ky
 
 
+def pbr_eig_grad(ctx, kappa, block, lam, weight, evecs, gC21, grho):
+    """Adds sum_s weight[s] d lambda_s / d (C21, rho) to gC21 (n x 21) and grho
+    (n); evecs holds the nvec eigenvectors one after another."""
+    kp, kk = _kappa(kappa)
+    lam = np.ascontiguousarray(np.asarray(lam, dtype=np.float64).reshape(-1))
+    w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64).reshape(-1))
+    if lam.size != w.size or lam.size < 1:
+        raise ValueError("lambda and weight must have the same positive length")
+    pv, ov, kv = _vec(evecs)
+    pc, oc, kc = _vec(gC21, np.float64)
+    pr, orr, kr = _vec(grho, np.float64)
+    _check(ctx, lib().pbr_eig_grad(ctx, kp, int(block), int(lam.size), lam.ctypes.data_as(_dp),
+                                   w.ctypes.data_as(_dp), pv, ov, pc, pr, _same_place(oc, orr)))
+    return kc, kr
+
+
 def pbr_precond(ctx, kappa, block, shift, r, z):
     kp, kk = _kappa(kappa)
     pr, orr, kr = _vec(r)
@@ -353,6 +371,9 @@ class Context:
 
     def apply_blocks(self, kappa, s, x, y):
         return pbr_apply_blocks(self.h, kappa, s, x, y)
+
+    def eig_grad(self, kappa, block, lam, weight, evecs, gC21, grho):
+        return pbr_eig_grad(self.h, kappa, block, lam, weight, evecs, gC21, grho)
 
     def precond(self, kappa, block, shift, r, z):
         return pbr_precond(self.h, kappa, block, shift, r, z)
