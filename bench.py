@@ -1,11 +1,14 @@
 """Benchmark: Bloch band path of the parity-blocked solver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 128] [--nk 16] [--nev 20]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube|fcc] [--n N] [--nk 16] [--nev M]
 
 Workload: two-phase unit cube, n^3 grid (default n = 128), cubic matrix
 (C11=1, C12=0.4, C44=0.3, rho=1) with a centred sphere r = 0.35 holding a seeded
 SPD stiffness (rho = 4); 16 points on the Gamma-X-M-Gamma-R path; the 20 lowest
 eigenpairs per point; shift delta = 0.30 C_max; tolerances 1e-12.
+--workload fcc: the paper's FCC cell (quartz matrix, silicon sphere, subpixel
+volume-fraction material; dimensionless units) at n = 60 on the 91-point
+Gamma-X-W-K-Gamma-L-U-W-L-K path with 40 eigenpairs per point.
 
 One step = the whole hot path over the path: at every k, four parity-block
 shift-invert Krylov solves advancing in lockstep (every launch covers all active
@@ -43,9 +46,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=0)
-    p.add_argument("--n", type=int, default=128)
-    p.add_argument("--nk", type=int, default=16)
-    p.add_argument("--nev", type=int, default=20)
+    p.add_argument("--workload", choices=("cube", "fcc"), default="cube",
+                   help="cube: the two-phase unit cube (default); fcc: the paper's quartz/Si "
+                        "FCC cell on its 91-point path")
+    p.add_argument("--n", type=int, default=0, help="grid size (default 128 cube, 60 fcc)")
+    p.add_argument("--nk", type=int, default=16, help="path points (cube workload)")
+    p.add_argument("--nev", type=int, default=0, help="eigenpairs per k (default 20 cube, 40 fcc)")
     p.add_argument("--first", type=int, default=0,
                    help="time only the first m points of the path (short profiled runs)")
     p.add_argument("--full-every", type=int, default=4,
@@ -139,7 +145,7 @@ def copy_peak(torch, nbytes=2 << 30, iters=20):
     return 2 * nbytes / t / 1e9
 
 
-def cpu_sample(n, kappa, C21, rho, delta):
+def cpu_sample(n, kappa, C21, rho, delta, A_lat=None):
     """Oracle (as written) cost of one PCG iteration's operator work at this n:
     one matvec (index formula) and one preconditioner application (numpy.fft),
     both in the full space, which is how the oracle evaluates a block too."""
@@ -151,9 +157,9 @@ def cpu_sample(n, kappa, C21, rho, delta):
     Cref, rref = F.reference_material(C21, rho)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        y = P.apply_A(x, (n, n, n), kappa, C21, rho, s=delta)
+        y = P.apply_A(x, (n, n, n), kappa, C21, rho, s=delta, A_lat=A_lat)
         t1 = time.perf_counter()
-        z = F.precond_fft(y, (n, n, n), kappa, -1, Cref, rref, delta)
+        z = F.precond_fft(y, (n, n, n), kappa, -1, Cref, rref, delta, A_lat)
         t2 = time.perf_counter()
     assert np.isfinite(z).all()
     return t1 - t0, t2 - t1
@@ -184,17 +190,27 @@ def main():
     import numpy as np
     import torch
     from paper_2606_03599_amd import pbr
-    from synth import sc_path, two_phase_cell
+    from synth import fcc_path, fcc_quartz_si_cell, sc_path, two_phase_cell
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    n = args.n
+    fcc = args.workload == "fcc"
+    n = args.n if args.n > 0 else (60 if fcc else 128)
+    nev = args.nev if args.nev > 0 else (40 if fcc else 20)
     dims = (n, n, n)
-    log(f"workload: two-phase cell n={n}, nk={args.nk}, nev={args.nev}")
-    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
-    ctx = pbr.Context(dims)
+    A_lat = None
+    if fcc:
+        C21, rho, A_lat, _ = fcc_quartz_si_cell(dims, supersample=4)
+        kappas, _ = fcc_path(10)
+        wl = (f"FCC cell (quartz matrix, silicon sphere R = a0/4, subpixel volume-fraction "
+              f"material) n={n}^3, 91-point Gamma-X-W-K-Gamma-L-U-W-L-K path")
+    else:
+        C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+        kappas, _ = sc_path(args.nk)
+        wl = f"two-phase unit cube n={n}^3, {args.nk}-point Gamma-X-M-Gamma-R path"
+    log(f"workload: {wl}, nev={nev}")
+    ctx = pbr.Context(dims, A_lat=A_lat)
     ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
     delta = ctx.default_shift()
-    kappas, _ = sc_path(args.nk)
     if args.first > 0:
         kappas = kappas[:args.first]
     kap_mv = (0.15, 0.05, 0.10)
@@ -243,11 +259,11 @@ def main():
     # ---- the timed steps: blocked band path ----
     for w in range(args.warmup):
         log(f"warmup {w}")
-        ctx.band_path(kappas, args.nev, blocked=True, opts=opts)
+        ctx.band_path(kappas, nev, blocked=True, opts=opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ev, st = ctx.band_path(kappas, args.nev, blocked=True, opts=opts)
+        ev, st = ctx.band_path(kappas, nev, blocked=True, opts=opts)
         log(f"step {k}: {st.seconds:.2f} s, op_applies {st.op_applies}, pcg avg {st.pcg_avg:.1f}")
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / max(1, args.steps)
@@ -257,12 +273,12 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 1),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"two-phase unit cube n={n}^3, {args.nk}-point Gamma-X-M-Gamma-R "
-                               f"path{'' if args.first <= 0 else f' (first {len(kappas)} points)'}, "
-                               f"{args.nev} lowest eigenpairs per k, 4 parity blocks with "
+        "config": {"workload": f"{wl}{'' if args.first <= 0 else f' (first {len(kappas)} points)'}, "
+                               f"{nev} lowest eigenpairs per k, 4 parity blocks with "
                                "certified merge, shift-invert Lanczos + FFT-preconditioned PCG, "
-                               "complex128", "n": n, "nk": args.nk, "nev": args.nev,
-                   "tol": 1e-12, "tol_inner": 1e-12, "radius": 0.35, "seed": 0,
+                               "complex128", "n": n, "nk": len(kappas), "nev": nev,
+                   "tol": 1e-12, "tol_inner": 1e-12,
+                   **({"lattice": "fcc", "supersample": 4} if fcc else {"radius": 0.35, "seed": 0}),
                    "blocks_per_launch": 1 if args.serial_blocks else 4},
         "kernels": kernels,
         "pcg_avg": round(st.pcg_avg, 2), "pcg_max": st.pcg_iters_max,
@@ -275,11 +291,11 @@ def main():
         sub = kappas[::args.full_every]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        evb, stb = ctx.band_path(sub, args.nev, blocked=True, opts=opts)
+        evb, stb = ctx.band_path(sub, nev, blocked=True, opts=opts)
         torch.cuda.synchronize()
         t_b = time.perf_counter() - t0
         t0 = time.perf_counter()
-        evf, stf = ctx.band_path(sub, args.nev, blocked=False)
+        evf, stf = ctx.band_path(sub, nev, blocked=False)
         torch.cuda.synchronize()
         t_f = time.perf_counter() - t0
         diff = float(np.max(np.abs(evb - evf) / np.abs(evf)))
@@ -293,7 +309,7 @@ def main():
     ctx.close()
     # ---- CPU oracle baseline (bounded sample, scaled to the path) ----
     if not args.no_cpu:
-        t_mv_cpu, t_pc_cpu = cpu_sample(n, kap_mv, C21, rho, delta)
+        t_mv_cpu, t_pc_cpu = cpu_sample(n, kap_mv, C21, rho, delta, A_lat)
         iters = st.pcg_iters_total
         est = iters * (t_mv_cpu + t_pc_cpu)
         out["cpu_baseline"] = {

@@ -158,7 +158,11 @@ pbr_status pbr_apply_blocks(pbr_ctx *c, const double kappa[3], double s, const v
 /* z = T_xi diag_m(K(m)^-1) T_xi^H r with K(m) = Bhat(m) C_ref Bhat(m)^H +
  * shift * rho_ref * I_3: the FFT-diagonal preconditioner of the shifted system
  * (Fourier bases of Sec. 5.1-5.2, symbols Eqs. 5.8-5.11; T_xi = T full,
- * T_sigma = T F_sigma for a block).  shift > 0. */
+ * T_sigma = T F_sigma for a block).  shift > 0.  Every transform length (n_l
+ * in the full space, n_l / 2 in a block) must be one of 1, 2, 3, 4, 5, 6, 8, 10,
+ * 12, 15, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120, 128, 160, 192, 240,
+ * 256 (PBR_EINVAL otherwise); the same holds for pbr_solve, pbr_eigs and the
+ * calls built on them with the preconditioner on. */
 pbr_status pbr_precond(pbr_ctx *c, const double kappa[3], int block, double shift,
                        const void *r, void *z, int on_device);
 

@@ -25,7 +25,7 @@
 //   3. k (y3) axis forward, fold + 3x3 Cholesky solves + unfold per mode,
 //      k axis inverse -- all in LDS;
 //   4. j axis inverse;   5. i axis inverse, times 1/N.
-// Every 1D transform is a mixed radix-4/2/3 Stockham FFT in LDS on a batch of
+// Every 1D transform is a mixed radix-4/2/3/5 Stockham FFT in LDS on a batch of
 // lines; lines along j and k are batched over consecutive i for coalescing.
 #include <cmath>
 #include <vector>
@@ -56,6 +56,26 @@ __device__ inline void small_dft(cplx* v) {
     v[2] = csub(t0, t2);
     v[1] = cadd(t1, t3);
     v[3] = csub(t1, t3);
+  } else if constexpr (R == 5) {
+    // X_k = sum_j x_j W^{jk}, W = e^{SIGN 2 pi i / 5}: with t = x1 + x4, x2 + x3
+    // and u = x1 - x4, x2 - x3, X_1,4 = a1 +- SIGN i b1, X_2,3 = a2 +- SIGN i b2
+    const double c1 = 0.30901699437494742410;   // cos(2 pi / 5)
+    const double c2 = -0.80901699437494742410;  // cos(4 pi / 5)
+    const double s1 = 0.95105651629515357212;   // sin(2 pi / 5)
+    const double s2 = 0.58778525229247312917;   // sin(4 pi / 5)
+    const cplx t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const cplx u1 = csub(v[1], v[4]), u2 = csub(v[2], v[3]);
+    const cplx a1 = cfma(c2, t2, cfma(c1, t1, v[0]));
+    const cplx a2 = cfma(c1, t2, cfma(c2, t1, v[0]));
+    const cplx b1 = cfma(s2, u2, cscale(s1, u1));
+    const cplx b2 = cfma(-s1, u2, cscale(s2, u1));
+    const cplx ib1 = (SIGN < 0) ? mk(b1.y, -b1.x) : mk(-b1.y, b1.x);  // SIGN i b1
+    const cplx ib2 = (SIGN < 0) ? mk(b2.y, -b2.x) : mk(-b2.y, b2.x);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, ib1);
+    v[4] = csub(a1, ib1);
+    v[2] = cadd(a2, ib2);
+    v[3] = csub(a2, ib2);
   } else {
     static_assert(R == 3, "radix");
     const double h = 0.86602540378443864676;  // sqrt(3)/2
@@ -69,13 +89,14 @@ __device__ inline void small_dft(cplx* v) {
   }
 }
 
-// Radix plan of a length 2^a 3^b, fixed at compile time: radix-4 stages, then
-// one radix-2 stage if needed, then radix-3 stages.
+// Radix plan of a length 2^a 3^b 5^c, fixed at compile time: radix-4 stages,
+// then one radix-2 stage if needed, then radix-3 and radix-5 stages.
 constexpr int plan_nfac(int L) {
   int n = 0;
   while (L % 4 == 0) { ++n; L /= 4; }
   while (L % 2 == 0) { ++n; L /= 2; }
   while (L % 3 == 0) { ++n; L /= 3; }
+  while (L % 5 == 0) { ++n; L /= 5; }
   return n;
 }
 constexpr int plan_fac(int L, int s) {
@@ -83,6 +104,7 @@ constexpr int plan_fac(int L, int s) {
   while (L % 4 == 0) { if (n == s) return 4; ++n; L /= 4; }
   while (L % 2 == 0) { if (n == s) return 2; ++n; L /= 2; }
   while (L % 3 == 0) { if (n == s) return 3; ++n; L /= 3; }
+  while (L % 5 == 0) { if (n == s) return 5; ++n; L /= 5; }
   return 1;
 }
 
@@ -520,8 +542,9 @@ int ensure_tables(pbr_ctx* c, bool blocked, const double kappa[3]) {
 }
 
 // ---- launch helpers: one kernel instance per supported transform length ----
-#define PBR_FFT_LENGTHS(X) \
-  X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+#define PBR_FFT_LENGTHS(X)                                                                 \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(30) X(32) X(40) \
+  X(48) X(60) X(64) X(80) X(96) X(120) X(128) X(160) X(192) X(240) X(256)
 
 typedef void (*LineKernel)(LineArgs);
 typedef void (*SolveKernel)(SolveArgs);
@@ -597,7 +620,7 @@ int run_lines(pbr_ctx* c, bool blocked, int nb, int axis, int sign, int mode, co
     k = sign < 0 ? line_kernel<1, 0, -1, 0>(LT) : line_kernel<1, 0, 1, 0>(LT);
   }
   if (!k) {
-    c->set_error("FFT lengths must be 2^a 3^b up to 256 (blocks: 512 along i)");
+    c->set_error("unsupported FFT length (2^a 3^b 5^c from the supported list, up to 256; blocks: n_l / 2)");
     return ST_EINVAL;
   }
   const int B = std::max(1, FFT_ELEMS / LM);
@@ -645,7 +668,7 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
   }
   const SolveKernel k = blocked ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
   if (!k) {
-    c->set_error("FFT lengths must be 2^a 3^b up to 256");
+    c->set_error("unsupported FFT length (2^a 3^b 5^c from the supported list, up to 256; blocks: n_l / 2)");
     return ST_EINVAL;
   }
   const int bi = solve_bi(S.L3, blocked ? 1 : 0);

@@ -17,6 +17,16 @@ from .materials import (
     batch_cells,
 )
 from .kpath import SC_POINTS, sc_path, split_intervals
+from .fcc import (
+    FCC_POINTS,
+    fcc_lattice,
+    fcc_path,
+    fcc_point,
+    fcc_quartz_si_cell,
+    frequency_hz,
+    quartz_stiffness,
+    silicon_stiffness,
+)
 from .vectors import complex_gaussian
 
 __all__ = [
@@ -32,4 +42,12 @@ __all__ = [
     "sc_path",
     "split_intervals",
     "complex_gaussian",
+    "FCC_POINTS",
+    "fcc_lattice",
+    "fcc_path",
+    "fcc_point",
+    "fcc_quartz_si_cell",
+    "frequency_hz",
+    "quartz_stiffness",
+    "silicon_stiffness",
 ]

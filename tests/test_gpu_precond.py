@@ -23,7 +23,8 @@ TOL = 1e-12
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2), (4, 4, 4), (8, 8, 8), (6, 12, 6), (16, 8, 4),
-                                  (24, 6, 12)])
+                                  (24, 6, 12), (10, 10, 10), (20, 6, 30), (30, 20, 10),
+                                  (60, 10, 4)])
 @pytest.mark.parametrize("A_lat", [None, "fcc"])
 def test_precond_matches_oracle(dims, A_lat):
     Al = FCC if A_lat == "fcc" else None

@@ -47,3 +47,24 @@ def test_batch_cells_uneven():
     ns = [c[0] for c in cells]
     assert set(ns) <= {64, 96, 128}
     assert all(0.2 <= c[1] <= 0.4 for c in cells)
+
+
+def test_fcc_materials_and_path():
+    """The FCC quartz/Si workload of Sec. 7: SPD stiffnesses, a silicon volume
+    fraction equal to the sphere's share of the cell, 91 path points through the
+    listed vertices."""
+    from synth import fcc_path, fcc_quartz_si_cell, quartz_stiffness, silicon_stiffness
+    for C in (quartz_stiffness(), silicon_stiffness()):
+        assert np.allclose(C, C.T) and np.linalg.eigvalsh(C).min() > 0
+    C21, rho, A, theta = fcc_quartz_si_cell((16, 16, 16), supersample=4)
+    assert theta.min() == 0.0 and theta.max() == 1.0
+    assert 0.0 < theta[(theta > 0) & (theta < 1)].size < theta.size
+    frac = 4.0 / 3.0 * np.pi * 0.25 ** 3 / abs(np.linalg.det(A))
+    assert abs(theta.mean() - frac) < 0.01 * frac
+    assert np.all((rho >= 2.329 - 1e-12) & (rho <= 2.65 + 1e-12))
+    for reading, X in (("reduced", (0, 0.5, 0.5)), ("cartesian", (0.5, 0.25, 0.25))):
+        ks, labels = fcc_path(10, reading)
+        assert ks.shape == (91, 3)
+        assert [labels[i] for i in sorted(labels)] == list("GXWKGLUWLK")
+        assert np.allclose(ks[10], X) and np.allclose(ks[40], (0, 0, 0))
+        assert np.allclose(ks[50], (0.5, 0.5, 0.5))  # L: both readings agree
