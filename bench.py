@@ -46,6 +46,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=0)
+    p.add_argument("--study", choices=("refinement",), default=None,
+                   help="refinement: grid-refinement errors of the FCC workload at X, W and L "
+                        "against a 256^3 blocked reference (one JSON line)")
     p.add_argument("--workload", choices=("cube", "fcc"), default="cube",
                    help="cube: the two-phase unit cube (default); fcc: the paper's quartz/Si "
                         "FCC cell on its 91-point path")
@@ -181,12 +184,45 @@ def traffic_record(kernel_src, name):
     return rec
 
 
+def refinement_study(grids=(16, 32, 64, 128), ref=256, nev=8, points=("X", "W", "L")):
+    """Relative eigenvalue errors of the FCC workload on coarser grids against the
+    blocked solve at ref^3, and the observed orders log2(e_n / e_2n)."""
+    import numpy as np
+    import torch
+    from paper_2606_03599_amd import pbr
+    from synth import fcc_point, fcc_quartz_si_cell
+    vals = {}
+    t0 = time.perf_counter()
+    for n in tuple(grids) + (ref,):
+        C21, rho, A, _ = fcc_quartz_si_cell((n, n, n), supersample=4)
+        ctx = pbr.Context((n, n, n), A_lat=A)
+        ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
+        del C21, rho
+        for p in points:
+            ev, st = ctx.eigs_merged(tuple(fcc_point(p)), nev)
+            vals[(n, p)] = np.asarray(ev)
+            log(f"refinement n={n} {p}: {np.round(ev[:4], 6)} ({time.perf_counter() - t0:.0f} s)")
+        ctx.close()
+        torch.cuda.empty_cache()
+    err = {p: {n: float(np.max(np.abs(vals[(n, p)] - vals[(ref, p)]) / vals[(ref, p)]))
+               for n in grids} for p in points}
+    order = {p: {f"{a}->{b}": round(float(np.log2(err[p][a] / err[p][b])), 3)
+                 for a, b in zip(grids[:-1], grids[1:])} for p in points}
+    return {"study": "grid refinement, FCC quartz/Si cell, blocked solves, max relative "
+                     f"error of the {nev} lowest eigenvalues vs {ref}^3",
+            "reference_n": ref, "grids": list(grids), "max_rel_error": err,
+            "observed_order": order, "seconds": round(time.perf_counter() - t0, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU: collectives and sharding are "
                                    "not part of it, so --gpus must be 1"}))
         sys.exit(2)
+    if args.study == "refinement":
+        print(json.dumps(refinement_study()), flush=True)
+        return
     import numpy as np
     import torch
     from paper_2606_03599_amd import pbr
