@@ -81,10 +81,13 @@ typedef struct pbr_opts {
   int precond;       /* 1 = FFT-diagonal preconditioner, 0 = none */
   int check_every;   /* PCG iterations between host convergence checks; 0 = automatic */
   int seed;          /* seed of the (deterministic) start vector */
-  int concurrent;    /* pbr_eigs_merged / blocked pbr_band_path: 1 = the four block
-                        solves run at once, one host thread and one HIP stream each
-                        (joined to the context stream before return); 0 = one after
-                        another on the context stream.  Results are identical. */
+  int concurrent;    /* pbr_eigs_merged / pbr_band_path: 1 = independent solves (the
+                        four blocks, and up to 4 wave vectors of a path) advance in
+                        lockstep, every kernel launch covering all of them; 0 = one
+                        solve after another.  Results are identical. */
+  int graphs;        /* 1 = each chunk of check_every PCG iterations is captured once
+                        as a HIP graph (per k, shift and set of layouts) and replayed;
+                        0 = kernels launched one by one.  Results are identical. */
 } pbr_opts;
 
 /* Statistics of one pbr_solve / pbr_eigs / pbr_eigs_merged / pbr_band_path call. */
@@ -103,7 +106,8 @@ typedef struct pbr_stats {
 } pbr_stats;
 
 /* Fill *o with the defaults: tol 1e-12, tol_inner 1e-12, maxit 300 / 200,
- * ncv automatic, precond 1, check_every automatic, seed 1, concurrent 1. */
+ * ncv automatic, precond 1, check_every automatic, seed 1, concurrent 1,
+ * graphs 1. */
 void pbr_opts_default(pbr_opts *o);
 
 /* Create a context for an n1 x n2 x n3 grid on HIP device `hip_device`.
@@ -198,8 +202,10 @@ pbr_status pbr_eigs_merged(pbr_ctx *c, const double kappa[3], int nev, double sh
 
 /* Band structure along nk reduced wave vectors kappas (nk x 3 row-major host
  * doubles): evals[q*nev + t] is the t-th eigenvalue at kappa q.  blocked = 1
- * uses pbr_eigs_merged at every point, blocked = 0 the full-space pbr_eigs.
- * st (optional) accumulates over the path. */
+ * gives pbr_eigs_merged's result at every point, blocked = 0 the full-space
+ * pbr_eigs'.  With opts->concurrent the path is processed 4 wave vectors at a
+ * time, all their solves in lockstep (16 block solves, or 4 full-space ones,
+ * per kernel launch).  st (optional) accumulates over the path. */
 pbr_status pbr_band_path(pbr_ctx *c, int nk, const double *kappas, int nev,
                          int blocked, double shift, const pbr_opts *opts,
                          double *evals, pbr_stats *st);

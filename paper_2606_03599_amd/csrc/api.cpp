@@ -59,7 +59,7 @@ pbr_opts resolve_opts(const pbr_opts* o) {
 int check_opts(pbr_ctx* c, const pbr_opts& o) {
   if (!(o.tol > 0) || !(o.tol_inner > 0) || o.maxit_outer < 0 || o.maxit_inner < 1 ||
       o.ncv < 0 || (o.precond != 0 && o.precond != 1) || o.check_every < 0 ||
-      (o.concurrent != 0 && o.concurrent != 1)) {
+      (o.concurrent != 0 && o.concurrent != 1) || (o.graphs != 0 && o.graphs != 1)) {
     c->set_error("invalid pbr_opts");
     return ST_EINVAL;
   }
@@ -129,6 +129,7 @@ void pbr_opts_default(pbr_opts* o) {
   o->check_every = 0;
   o->seed = 1;
   o->concurrent = 1;
+  o->graphs = 1;
 }
 
 pbr_status pbr_create(pbr_ctx** out, int n1, int n2, int n3, const double* A_lat, int hip_device,
@@ -231,6 +232,9 @@ void pbr_destroy(pbr_ctx* c) {
     dev_free(W.ppart);
     dev_free(W.Wnull);
   }
+  if (c->pcg_graph.exec) (void)hipGraphExecDestroy(c->pcg_graph.exec);
+  if (c->pcg_graph.graph) (void)hipGraphDestroy(c->pcg_graph.graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   dev_free(c->st_all);
   if (c->hpinned) (void)hipHostFree(c->hpinned);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -445,6 +449,7 @@ pbr_status pbr_apply_blocks(pbr_ctx* c, const double kappa[3], double s, const v
   ApplyLayout L[4];
   for (int b = 0; b < 4; ++b) {
     L[b].block = b;
+    for (int l = 0; l < 3; ++l) L[b].ph[l] = g.ph[l];
     L[b].x = sx.dev + b * nb3;
     L[b].y = sy.dev + b * nb3;
   }
@@ -610,38 +615,33 @@ pbr_status pbr_band_path(pbr_ctx* c, int nk, const double* kappas, int nev, int 
     c->set_error("nk >= 1, kappas, evals non-NULL and nev >= 1 required");
     return PBR_EINVAL;
   }
-  if (blocked) {
-    int s = check_block(c, 0);
-    if (s != ST_OK) return (pbr_status)s;
+  const pbr_opts o = resolve_opts(opts);
+  int st = check_block(c, blocked ? 0 : -1);
+  for (int q = 0; st == ST_OK && q < nk; ++q) st = check_kappa(c, kappas + 3 * q);
+  if (st == ST_OK) st = check_opts(c, o);
+  if (st == ST_OK && !std::isfinite(shift)) {
+    c->set_error("shift must be finite");
+    st = ST_EINVAL;
+  }
+  if (st == ST_OK) st = check_material(c);
+  if (st != ST_OK) return (pbr_status)st;
+  hipSetDevice(c->device);
+  if (!(shift > 0.0)) shift = pbr_default_shift(c);
+  const long dim = 3 * c->layout_nodes(blocked ? 0 : -1);
+  if (!blocked && nev >= dim - 12) {
+    c->set_error("nev must be below the dimension minus the Gamma null modes");
+    return PBR_EINVAL;
   }
   auto t0 = std::chrono::steady_clock::now();
   pbr_stats acc;
   std::memset(&acc, 0, sizeof(acc));
-  int status = PBR_OK;
-  for (int q = 0; q < nk; ++q) {
-    pbr_stats one;
-    pbr_status s;
-    if (blocked)
-      s = pbr_eigs_merged(c, kappas + 3 * q, nev, shift, opts, evals + (long)q * nev, &one);
-    else
-      s = pbr_eigs(c, kappas + 3 * q, -1, nev, shift, opts, evals + (long)q * nev, nullptr, 0,
-                   &one);
-    if (s != PBR_OK && s != PBR_ENOCONV) return s;
-    if (s == PBR_ENOCONV) status = PBR_ENOCONV;
-    acc.outer_iters += one.outer_iters;
-    acc.op_applies += one.op_applies;
-    acc.pcg_iters_total += one.pcg_iters_total;
-    acc.pcg_iters_max = std::max(acc.pcg_iters_max, one.pcg_iters_max);
-    acc.matvecs += one.matvecs;
-    acc.n_zero += one.n_zero;
-    acc.converged += one.converged;
-    acc.max_rel_resid = std::max(acc.max_rel_resid, one.max_rel_resid);
-    for (int b = 0; b < 4; ++b) acc.nev_block[b] = one.nev_block[b];
-  }
+  st = blocked ? merged_path(c, nk, kappas, nev, shift, o, evals, &acc)
+               : full_path(c, nk, kappas, nev, shift, o, evals, &acc);
+  if (st != ST_OK && st != ST_ENOCONV) return (pbr_status)st;
   acc.pcg_avg = acc.op_applies ? (double)acc.pcg_iters_total / acc.op_applies : 0.0;
   acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = acc;
-  return (pbr_status)status;
+  return (pbr_status)st;
 }
 
 }  // extern "C"

@@ -11,8 +11,10 @@
 #include "common.hpp"
 #include "geometry.hpp"
 
-// Layouts batched into one launch at most: the four parity blocks.
-#define PBR_MAX_BATCH 4
+// k-points whose solves can run in lockstep (each with its own work areas and
+// FFT tables), and layouts batched into one launch at most: 4 blocks per k-point.
+#define PBR_KSLOTS 4
+#define PBR_MAX_BATCH (4 * PBR_KSLOTS)
 // Doubles of pinned host scratch per context.
 #define PBR_PINNED 32768
 
@@ -72,11 +74,26 @@ struct pbr_ctx {
   double rho_ref = 1.0;
   std::vector<double> rho_host;   // natural order
   DevMaterial mat[5];  // index 0 = natural (full), 1..4 = blocks 0..3
-  FftTables fft[5];
-  LayoutWork work[5];
+  FftTables fft[2 * PBR_KSLOTS];     // [slot][natural, blocks]
+  LayoutWork work[5 * PBR_KSLOTS];   // [slot][natural, block 0..3]
 
   double* hpinned = nullptr;      // pinned host scratch (PBR_PINNED doubles)
-  PcgScalars* st_all = nullptr;   // device CG scalars of the 5 layouts, contiguous
+  PcgScalars* st_all = nullptr;   // device CG scalars of all work areas, contiguous
+  // One captured chunk of fused PCG iterations, replayed while its launch
+  // arguments (layouts, vectors, k, shift, chunk length) stay the same.
+  struct PcgGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int nb = 0, chunk = 0;
+    int blocks[PBR_MAX_BATCH] = {};
+    int slots[PBR_MAX_BATCH] = {};
+    double kap[PBR_MAX_BATCH][3] = {};
+    const void* b[PBR_MAX_BATCH] = {};
+    const void* x[PBR_MAX_BATCH] = {};
+    double shift = 0.0;
+  } pcg_graph;
+  hipStream_t cap_stream = nullptr;  // capture stream (the context stream may be the null stream)
+  bool graphs_broken = false;        // capture failed once: launch eagerly from then on
 
   std::string err;
   std::mutex err_mu;
@@ -86,6 +103,8 @@ struct pbr_ctx {
   }
 
   DevMaterial& material(int block) { return mat[block + 1]; }
+  LayoutWork& wk(int slot, int block) { return work[5 * slot + block + 1]; }
+  FftTables& tables(int slot, bool blocked) { return fft[2 * slot + (blocked ? 1 : 0)]; }
   long layout_nodes(int block) const { return block < 0 ? n : n / 4; }
 };
 
@@ -102,7 +121,9 @@ Geo make_geo(const pbr_ctx* c, int block, const double kappa[3]);
 // with alpha from the (p, q) partials of the matvec (or r = b, x = 0 at init),
 // z the transform buffer, pout = z + beta p (p at init).
 struct PcgStep {
+  int slot = 0;       // work area / FFT tables of this layout's k-point
   int block = -1;
+  double kappa[3] = {0, 0, 0};
   PcgScalars* st = nullptr;
   int init = 0;
   double tol2 = 0.0;
@@ -125,13 +146,14 @@ struct PcgStep {
 // Re(x^H y) to part.
 struct ApplyLayout {
   int block = -1;
+  cplx ph[3] = {{1, 0}, {1, 0}, {1, 0}};  // e^{i phi_l} of this layout's k
   const cplx* x = nullptr;
   cplx* y = nullptr;
   PcgScalars* st = nullptr;
   double* part = nullptr;
 };
-// nb layouts of one kind (all blocks, or the natural layout alone) in one
-// launch; g is the geometry of any of them (the class bits come from L[t].block);
+// nb layouts of one kind (parity blocks, or natural layouts) in one launch;
+// g is the geometry of any of them (class bits and Bloch phases come from L[t]);
 // *nparts receives the partials per layout.
 int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,
                        long part_cap = 0, int* nparts = nullptr);
@@ -142,9 +164,15 @@ int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, c
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
                    const cplx* r, cplx* z);
 // The preconditioner passes of one fused PCG iteration (five launches) for nb
-// layouts of one kind at once; P[t].block names the layout.
-int launch_pcg_precond_batch(pbr_ctx* c, const double kappa[3], int nb, const PcgStep* P,
-                             double shift);
+// layouts of one kind at once; P[t] names the layout (slot, block, kappa).
+int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift);
+
+// A layout of a batched solve: work area (slot, block) at wave vector kappa.
+struct LayoutRef {
+  int slot = 0;
+  int block = -1;
+  double kappa[3] = {0, 0, 0};
+};
 
 // Adds sum_s w[s] d lambda_s / d (C21, rho) of nvec M-normalised eigenvectors v
 // (vector-major, layout `block`) to the natural-order fields gC (n x 21), grho.
@@ -152,10 +180,16 @@ int launch_eig_grad(pbr_ctx* c, const Geo& g, int block, int nvec, const double*
                     const double* w, const cplx* v, double* gC, double* grho);
 
 // solver drivers (solver.cpp)
-int ensure_work(pbr_ctx* c, int block);
+int ensure_work(pbr_ctx* c, int slot, int block);
 int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b, cplx* x,
               const pbr_opts& o, int* iters, int* conv);
 int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double shift,
                  const pbr_opts& o, double* evals, cplx* evecs_dev, pbr_stats* st);
 int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const pbr_opts& o,
                 double* evals, pbr_stats* st);
+// Blocked (certified merge) and full-space eigenvalues along nk wave vectors
+// (kappas: nk x 3, evals: nk x nev), up to PBR_KSLOTS k-points in lockstep.
+int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
+                const pbr_opts& o, double* evals, pbr_stats* st);
+int full_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
+              const pbr_opts& o, double* evals, pbr_stats* st);

@@ -153,13 +153,13 @@ struct LineArgs {
   long nlines;       // lines per component
   long N;
   const cplx* __restrict__ roots;
-  const cplx* __restrict__ twist;  // e^{-i y phi / L}, y in [0, L) of the transform
   double scale;
   struct {
     const cplx* in;
     cplx* out;
-    PcgHook h;       // fused PCG work (h.st == nullptr: plain transform)
-  } b[PBR_MAX_BATCH];  // layout blockIdx.z of the batch
+    const cplx* twist;  // e^{-i y phi / L}, y in [0, L) of the transform, this layout's k
+    PcgHook h;          // fused PCG work (h.st == nullptr: plain transform)
+  } b[PBR_MAX_BATCH];   // layout blockIdx.z of the batch
 };
 
 // First work-group of a PCG launch: finish the partials of the previous launch.
@@ -198,6 +198,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   const PcgHook& H = A.b[blockIdx.z].h;
   const cplx* in_ = A.b[blockIdx.z].in;
   cplx* out_ = A.b[blockIdx.z].out;
+  const cplx* __restrict__ twist = A.b[blockIdx.z].twist;
   PcgScalars* st = H.st;
   const bool first_wg = blockIdx.x == 0 && blockIdx.y == 0;
   if (st && !(MODE == 1 && H.init) && st->done) return;  // uniform per work-group
@@ -271,7 +272,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
       }
       const int slot = SPLIT ? 2 * b + (e & 1) : b;
       const int y = SPLIT ? e >> 1 : e;
-      if (SIGN < 0) x = cmul(x, A.twist[y]);
+      if (SIGN < 0) x = cmul(x, twist[y]);
       buf0[slot * LT + y] = x;
     }
   }
@@ -294,7 +295,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
       const int slot = SPLIT ? 2 * b + (e & 1) : b;
       const int y = SPLIT ? e >> 1 : e;
       cplx x = res[slot * LT + y];
-      if (SIGN > 0) x = cmul(x, cconj(A.twist[y]));
+      if (SIGN > 0) x = cmul(x, cconj(twist[y]));
       const long idx = co + base_of(l0 + b) + e * es;
       if (MODE == 2 && !H.init)
         out_[idx] = cfma(beta, out_[idx], cscale(A.scale, x));
@@ -312,10 +313,6 @@ struct SolveArgs {
   int L1, L2, L3;
   long N;
   const cplx* __restrict__ roots;  // length-L3 roots
-  const cplx* __restrict__ twist;  // e^{-i y phi3 / L3}
-  const cplx* __restrict__ e1;     // e^{i alpha_m} = e^{i (phi1 + 2 pi m)/n1}, m < n1
-  const cplx* __restrict__ e2;     // e^{i beta_q},  q < n2
-  const cplx* __restrict__ e3;     // e^{i gamma_r}, r < n3
   double cf[3][5];
   double Cref[21];
   double shift_rho;
@@ -324,6 +321,10 @@ struct SolveArgs {
     PcgScalars* st;   // fused PCG: skip once converged, write (r, z) partials
     double* part_out;
     int a, c;         // block class bits
+    const cplx* twist;  // e^{-i y phi3 / L3} of this layout's k
+    const cplx* e1;     // e^{i alpha_m} = e^{i (phi1 + 2 pi m)/n1}, m < n1
+    const cplx* e2;     // e^{i beta_q},  q < n2
+    const cplx* e3;     // e^{i gamma_r}, r < n3
   } b[PBR_MAX_BATCH];   // layout blockIdx.y of the batch
 };
 
@@ -413,6 +414,10 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   PcgScalars* const st = S.b[blockIdx.y].st;
   double* const part_out = S.b[blockIdx.y].part_out;
   const int ca = S.b[blockIdx.y].a, cc = S.b[blockIdx.y].c;
+  const cplx* __restrict__ twist = S.b[blockIdx.y].twist;
+  const cplx* __restrict__ e1 = S.b[blockIdx.y].e1;
+  const cplx* __restrict__ e2 = S.b[blockIdx.y].e2;
+  const cplx* __restrict__ e3 = S.b[blockIdx.y].e3;
   if (st && st->done) return;
   const int groups_i = (S.L1 + BI - 1) / BI;
   const int q = blockIdx.x / groups_i;
@@ -426,12 +431,12 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     const int comp = rem / BI, di = rem - comp * BI;
     if (di < bi)
       buf0[(comp * BI + di) * L3T + y] =
-          cmul(data[comp * S.N + base + di + y * kstride], S.twist[y]);
+          cmul(data[comp * S.N + base + di + y * kstride], twist[y]);
   }
   __syncthreads();
   cplx* f = fft_stages<L3T, 0, 1, -1>(S.roots, buf0, buf1, NL);
   cplx* g = (f == buf0) ? buf1 : buf0;
-  const cplx Eb = S.e2[q];
+  const cplx Eb = e2[q];
   double rz = 0.0;  // sum over this work-group's modes of Re(c^H K^-1 c)
   if (!BLK) {
     for (int w = threadIdx.x; w < bi * L3T; w += blockDim.x) {
@@ -439,7 +444,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       cplx bv[3], xv[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) bv[a] = f[(a * BI + di) * L3T + r];
-      mode_solve(S, S.e1[i0 + di], Eb, S.e3[r], bv, xv);
+      mode_solve(S, e1[i0 + di], Eb, e3[r], bv, xv);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         g[(a * BI + di) * L3T + r] = xv[a];
@@ -452,7 +457,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     for (int w = threadIdx.x; w < (bi / 2) * L3T; w += blockDim.x) {
       const int dp = w / L3T, r = w - dp * L3T;
       const int m1p = (i0 >> 1) + dp;
-      const cplx Ea = S.e1[m1p], Eg = S.e3[r];
+      const cplx Ea = e1[m1p], Eg = e3[r];
       // T_p = e^{-i(o2 beta + o3 gamma)}: conj(Eb)^o2 conj(Eg)^o3
       const cplx cb = cconj(Eb), cg = cconj(Eg);
       const cplx one = mk(1.0, 0.0);
@@ -490,7 +495,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     const int comp = rem / BI, di = rem - comp * BI;
     if (di < bi)
       data[comp * S.N + base + di + y * kstride] =
-          cmul(res[(comp * BI + di) * L3T + y], cconj(S.twist[y]));
+          cmul(res[(comp * BI + di) * L3T + y], cconj(twist[y]));
   }
 }
 
@@ -512,8 +517,8 @@ __global__ void table_kernel(int L, double phi, int kind, cplx* out) {
 // Tables of a layout kind (natural: slot 0; parity blocks, which share the box
 // shape: slot 1): for each transform length Lt[l] (axis 0 of a block: n1/2) the
 // roots and the twist, and the mode phases e^{i(phi_l + 2 pi t)/n_l}.
-int ensure_tables(pbr_ctx* c, bool blocked, const double kappa[3]) {
-  FftTables& T = c->fft[blocked ? 1 : 0];
+int ensure_tables(pbr_ctx* c, int slot, bool blocked, const double kappa[3]) {
+  FftTables& T = c->tables(slot, blocked);
   const int Lt[3] = {blocked ? c->n1 / 2 : c->n1, blocked ? c->n2 / 2 : c->n2,
                      blocked ? c->n3 / 2 : c->n3};
   const int nf[3] = {c->n1, c->n2, c->n3};
@@ -577,16 +582,17 @@ SolveKernel solve_kernel(int L) {
 
 // One pass of lines along `axis` for nb layouts of one kind; mode 1 / 2 are
 // the first / last PCG pass.  *nparts receives the partials per layout that a
-// mode-1 launch writes.
+// mode-1 launch writes.  T supplies the transform length and roots (the same
+// for every layout of the batch); each layout brings its own twist.
 struct LineIO {
   const cplx* in;
   cplx* out;
+  const cplx* twist;
   PcgHook h;
 };
 
-int run_lines(pbr_ctx* c, bool blocked, int nb, int axis, int sign, int mode, const LineIO* io,
-              double scale, long part_cap, int* nparts) {
-  FftTables& T = c->fft[blocked ? 1 : 0];
+int run_lines(pbr_ctx* c, const FftTables& T, bool blocked, int nb, int axis, int sign, int mode,
+              const LineIO* io, double scale, long part_cap, int* nparts) {
   const long N = c->layout_nodes(blocked ? 0 : -1);
   LineArgs A;
   A.L1 = c->n1;
@@ -598,11 +604,11 @@ int run_lines(pbr_ctx* c, bool blocked, int nb, int axis, int sign, int mode, co
   A.nlines = N / LM;
   A.N = N;
   A.roots = T.roots[axis];
-  A.twist = T.twist[axis];
   A.scale = scale;
   for (int t = 0; t < nb; ++t) {
     A.b[t].in = io[t].in;
     A.b[t].out = io[t].out;
+    A.b[t].twist = io[t].twist;
     A.b[t].h = io[t].h;
   }
   LineKernel k = nullptr;
@@ -640,21 +646,18 @@ struct SolveIO {
   cplx* data;
   PcgScalars* st;
   double* part_out;
+  const FftTables* T;  // this layout's k-point tables
 };
 
 int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift, long part_cap,
               int* nparts) {
-  FftTables& T = c->fft[blocked ? 1 : 0];
+  const FftTables& T = *io[0].T;
   SolveArgs S;
   S.L1 = c->n1;
   S.L2 = blocked ? c->n2 / 2 : c->n2;
   S.L3 = blocked ? c->n3 / 2 : c->n3;
   S.N = c->layout_nodes(blocked ? 0 : -1);
   S.roots = T.roots[2];
-  S.twist = T.twist[2];
-  S.e1 = T.post[0];
-  S.e2 = T.post[1];
-  S.e3 = T.post[2];
   for (int m = 0; m < 3; ++m)
     for (int d = 0; d < 5; ++d) S.cf[m][d] = c->cf[m][d];
   for (int qq = 0; qq < 21; ++qq) S.Cref[qq] = c->Cref[qq];
@@ -665,6 +668,10 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
     S.b[t].part_out = io[t].part_out;
     S.b[t].a = io[t].block >= 0 ? io[t].block >> 1 : 0;
     S.b[t].c = io[t].block >= 0 ? io[t].block & 1 : 0;
+    S.b[t].twist = io[t].T->twist[2];
+    S.b[t].e1 = io[t].T->post[0];
+    S.b[t].e2 = io[t].T->post[1];
+    S.b[t].e3 = io[t].T->post[2];
   }
   const SolveKernel k = blocked ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
   if (!k) {
@@ -689,32 +696,38 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, const cplx* r,
                    cplx* z) {
   const bool blocked = block >= 0;
-  PBR_TRY(ensure_tables(c, blocked, kappa));
+  PBR_TRY(ensure_tables(c, 0, blocked, kappa));
+  const FftTables& T = c->tables(0, blocked);
   const long N = c->layout_nodes(block);
-  LineIO a{r, z, PcgHook()}, b{z, z, PcgHook()};
-  SolveIO s{block, z, nullptr, nullptr};
-  PBR_TRY(run_lines(c, blocked, 1, 0, -1, 0, &a, 1.0, 0, nullptr));
-  PBR_TRY(run_lines(c, blocked, 1, 1, -1, 0, &b, 1.0, 0, nullptr));
+  LineIO a{r, z, nullptr, PcgHook()}, b{z, z, nullptr, PcgHook()};
+  SolveIO s{block, z, nullptr, nullptr, &T};
+  LineIO a0 = a, b0 = b, b1 = b;
+  a0.twist = T.twist[0];
+  b0.twist = T.twist[1];
+  b1.twist = T.twist[0];
+  PBR_TRY(run_lines(c, T, blocked, 1, 0, -1, 0, &a0, 1.0, 0, nullptr));
+  PBR_TRY(run_lines(c, T, blocked, 1, 1, -1, 0, &b0, 1.0, 0, nullptr));
   PBR_TRY(run_solve(c, blocked, 1, &s, shift, 0, nullptr));
-  PBR_TRY(run_lines(c, blocked, 1, 1, +1, 0, &b, 1.0, 0, nullptr));
-  PBR_TRY(run_lines(c, blocked, 1, 0, +1, 0, &b, 1.0 / (double)N, 0, nullptr));
+  PBR_TRY(run_lines(c, T, blocked, 1, 1, +1, 0, &b0, 1.0, 0, nullptr));
+  PBR_TRY(run_lines(c, T, blocked, 1, 0, +1, 0, &b1, 1.0 / (double)N, 0, nullptr));
   return ST_OK;
 }
 
-int launch_pcg_precond_batch(pbr_ctx* c, const double kappa[3], int nb, const PcgStep* P,
-                             double shift) {
+int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift) {
   if (nb < 1 || nb > PBR_MAX_BATCH) {
-    c->set_error("batch of 1 to 4 layouts expected");
+    c->set_error("batch of 1 to PBR_MAX_BATCH layouts expected");
     return ST_EINVAL;
   }
   const bool blocked = P[0].block >= 0;
-  PBR_TRY(ensure_tables(c, blocked, kappa));
+  for (int t = 0; t < nb; ++t) PBR_TRY(ensure_tables(c, P[t].slot, blocked, P[t].kappa));
+  const FftTables& T0 = c->tables(P[0].slot, blocked);
   const long N = c->layout_nodes(P[0].block);
   const long cap = P[0].part_cap;
   LineIO io1[PBR_MAX_BATCH], io2[PBR_MAX_BATCH], io4[PBR_MAX_BATCH], io5[PBR_MAX_BATCH];
   SolveIO sio[PBR_MAX_BATCH];
   int n_rr = 0, n_rz = 0;
   for (int t = 0; t < nb; ++t) {
+    const FftTables& T = c->tables(P[t].slot, blocked);
     PcgHook h;
     h.st = P[t].st;
     h.init = P[t].init;
@@ -730,22 +743,22 @@ int launch_pcg_precond_batch(pbr_ctx* c, const double kappa[3], int nb, const Pc
     h1.red_in = P[t].part_pq;
     h1.red_n = P[t].n_pq;
     h1.part_out = P[t].part_rr;
-    io1[t] = LineIO{nullptr, P[t].z, h1};
-    io2[t] = LineIO{P[t].z, P[t].z, h};
+    io1[t] = LineIO{nullptr, P[t].z, T.twist[0], h1};
+    io2[t] = LineIO{P[t].z, P[t].z, T.twist[1], h};
     io2[t].h.role = 1;  // first work-group finishes |r|^2 and the convergence test
     io2[t].h.red_in = P[t].part_rr;
-    io4[t] = LineIO{P[t].z, P[t].z, h};
+    io4[t] = LineIO{P[t].z, P[t].z, T.twist[1], h};
     io4[t].h.role = 2;  // first work-group finishes (r, z) and beta
     io4[t].h.red_in = P[t].part_rz;
-    io5[t] = LineIO{P[t].z, P[t].pout, h};  // p = z + beta p
-    sio[t] = SolveIO{P[t].block, P[t].z, P[t].st, P[t].part_rz};
+    io5[t] = LineIO{P[t].z, P[t].pout, T.twist[0], h};  // p = z + beta p
+    sio[t] = SolveIO{P[t].block, P[t].z, P[t].st, P[t].part_rz, &T};
   }
-  PBR_TRY(run_lines(c, blocked, nb, 0, -1, 1, io1, 1.0, cap, &n_rr));
+  PBR_TRY(run_lines(c, T0, blocked, nb, 0, -1, 1, io1, 1.0, cap, &n_rr));
   for (int t = 0; t < nb; ++t) io2[t].h.red_n = n_rr;
-  PBR_TRY(run_lines(c, blocked, nb, 1, -1, 0, io2, 1.0, cap, nullptr));
+  PBR_TRY(run_lines(c, T0, blocked, nb, 1, -1, 0, io2, 1.0, cap, nullptr));
   PBR_TRY(run_solve(c, blocked, nb, sio, shift, cap, &n_rz));
   for (int t = 0; t < nb; ++t) io4[t].h.red_n = n_rz;
-  PBR_TRY(run_lines(c, blocked, nb, 1, +1, 0, io4, 1.0, cap, nullptr));
-  PBR_TRY(run_lines(c, blocked, nb, 0, +1, 2, io5, 1.0 / (double)N, cap, nullptr));
+  PBR_TRY(run_lines(c, T0, blocked, nb, 1, +1, 0, io4, 1.0, cap, nullptr));
+  PBR_TRY(run_lines(c, T0, blocked, nb, 0, +1, 2, io5, 1.0 / (double)N, cap, nullptr));
   return ST_OK;
 }

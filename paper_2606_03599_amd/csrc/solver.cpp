@@ -24,6 +24,7 @@ typedef std::complex<double> zc;
 namespace {
 
 constexpr int SMALL_CPLX = 8192;  // capacity of LayoutWork::small
+constexpr int NSTATE = 5 * PBR_KSLOTS;  // device CG scalar sets (one per work area)
 
 int alloc_vec(pbr_ctx* c, cplx** p, long n3) { return dev_alloc(c, (void**)p, sizeof(cplx) * n3); }
 
@@ -79,8 +80,8 @@ int upload_small(pbr_ctx* c, cplx* dev, const std::vector<zc>& h) {
 // M-orthonormal basis of N_Gamma.  Full space: chi in {1, (-1)^{i+j},
 // (-1)^{i+k}, (-1)^{j+k}} (4 fields); a block: all four are +-1 on the class,
 // so one field sqrt(rho)/sqrt(sum rho).
-int ensure_null_fields(pbr_ctx* c, int block) {
-  LayoutWork& W = c->work[block + 1];
+int ensure_null_fields(pbr_ctx* c, int slot, int block) {
+  LayoutWork& W = c->wk(slot, block);
   if (W.Wnull) return ST_OK;
   const long N = W.N;
   std::vector<double> rho(N);
@@ -181,8 +182,8 @@ double vnorm(pbr_ctx* c, LayoutWork& W, const cplx* v, int* status) {
 
 }  // namespace
 
-int ensure_work(pbr_ctx* c, int block) {
-  LayoutWork& W = c->work[block + 1];
+int ensure_work(pbr_ctx* c, int slot, int block) {
+  LayoutWork& W = c->wk(slot, block);
   const long N = c->layout_nodes(block);
   if (W.N == N && W.x) return ST_OK;
   W.N = N;
@@ -200,8 +201,8 @@ int ensure_work(pbr_ctx* c, int block) {
   PBR_TRY(dev_alloc(c, (void**)&W.part, sizeof(double) * 1024 * 2 * 128));
   PBR_TRY(dev_alloc(c, (void**)&W.part2, sizeof(double) * 1024 * 2));
   PBR_TRY(dev_alloc(c, (void**)&W.dscal, sizeof(double) * 4096));
-  if (!c->st_all) PBR_TRY(dev_alloc(c, (void**)&c->st_all, sizeof(PcgScalars) * 5));
-  W.st = c->st_all + (block + 1);
+  if (!c->st_all) PBR_TRY(dev_alloc(c, (void**)&c->st_all, sizeof(PcgScalars) * NSTATE));
+  W.st = c->st_all + (5 * slot + block + 1);
   W.pcap = N / 128 + 4096;
   PBR_TRY(dev_alloc(c, (void**)&W.ppart, sizeof(double) * 3 * W.pcap));
   return ST_OK;
@@ -209,19 +210,22 @@ int ensure_work(pbr_ctx* c, int block) {
 
 namespace {
 
-// Device CG scalars of all five layouts in one copy.
-int read_states(pbr_ctx* c, PcgScalars hs[5]) {
-  PBR_HIP(c, hipMemcpyAsync(c->hpinned, c->st_all, sizeof(PcgScalars) * 5,
+// Device CG scalars of all work areas in one copy.
+int read_states(pbr_ctx* c, PcgScalars hs[NSTATE]) {
+  static_assert(sizeof(PcgScalars) * NSTATE <= sizeof(double) * PBR_PINNED, "staging");
+  PBR_HIP(c, hipMemcpyAsync(c->hpinned, c->st_all, sizeof(PcgScalars) * NSTATE,
                             hipMemcpyDeviceToHost, c->stream));
   PBR_HIP(c, hipStreamSynchronize(c->stream));
-  std::memcpy(hs, c->hpinned, sizeof(PcgScalars) * 5);
+  std::memcpy(hs, c->hpinned, sizeof(PcgScalars) * NSTATE);
   return ST_OK;
 }
 
+int state_index(int slot, int block) { return 5 * slot + block + 1; }
+
 // Unpreconditioned CG of one layout (kept for pbr_opts.precond = 0).
-int pcg_plain(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b,
-              cplx* x, const pbr_opts& o) {
-  LayoutWork& W = c->work[block + 1];
+int pcg_plain(pbr_ctx* c, int slot, int block, const double kappa[3], double shift,
+              const cplx* b, cplx* x, const pbr_opts& o) {
+  LayoutWork& W = c->wk(slot, block);
   const hipStream_t SO = c->stream;
   const long n3 = 3 * W.N;
   const Geo g = make_geo(c, block, kappa);
@@ -232,7 +236,8 @@ int pcg_plain(pbr_ctx* c, int block, const double kappa[3], double shift, const 
   PBR_TRY(vec_copy(c, SO, n3, W.z, W.p));
   PBR_TRY(pcg_init_async(c, SO, n3, W.r, W.z, o.tol_inner, W.part, W.part2, W.st));
   int done_iters = 0;
-  PcgScalars hs[5];
+  PcgScalars hs[NSTATE];
+  const int si = state_index(slot, block);
   for (;;) {
     const int todo = std::min(chunk, o.maxit_inner - done_iters);
     if (todo <= 0) break;
@@ -244,8 +249,71 @@ int pcg_plain(pbr_ctx* c, int block, const double kappa[3], double shift, const 
       PBR_TRY(pcg_beta_p(c, SO, n3, W.r, W.z, W.p, W.part, W.st));
     }
     PBR_TRY(read_states(c, hs));
-    done_iters = hs[block + 1].iters;
-    if (hs[block + 1].done) break;
+    done_iters = hs[si].iters;
+    if (hs[si].done) break;
+  }
+  return ST_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// The captured chunk for these launch arguments, captured now if the cached
+// one was made for others.  Capture runs on the context's own capture stream
+// (the context stream may be the null stream, which cannot be captured); the
+// graph is launched on the context stream.  A failed capture switches graphs
+// off for the context (the eager launches give the same results).
+template <class F>
+int ensure_pcg_graph(pbr_ctx* c, int nb, const LayoutRef* L, const cplx* const* b,
+                     cplx* const* x, double shift, int chunk, F&& iterate) {
+  pbr_ctx::PcgGraph& G = c->pcg_graph;
+  bool same = G.exec && G.nb == nb && G.chunk == chunk && G.shift == shift;
+  for (int t = 0; same && t < nb; ++t)
+    same = G.blocks[t] == L[t].block && G.slots[t] == L[t].slot && G.b[t] == b[t] &&
+           G.x[t] == x[t] && G.kap[t][0] == L[t].kappa[0] && G.kap[t][1] == L[t].kappa[1] &&
+           G.kap[t][2] == L[t].kappa[2];
+  if (same) return ST_OK;
+  if (G.exec) (void)hipGraphExecDestroy(G.exec);
+  if (G.graph) (void)hipGraphDestroy(G.graph);
+  G = pbr_ctx::PcgGraph();
+  if (!c->cap_stream &&
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->graphs_broken = true;
+    return ST_OK;
+  }
+  const hipStream_t saved = c->stream;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->graphs_broken = true;
+    return ST_OK;
+  }
+  c->stream = c->cap_stream;
+  const int s = iterate(chunk);
+  c->stream = saved;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  if (s != ST_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess || !graph ||
+      hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    G.exec = nullptr;
+    c->graphs_broken = true;
+    (void)hipGetLastError();
+    return ST_OK;
+  }
+  G.graph = graph;
+  G.nb = nb;
+  G.chunk = chunk;
+  G.shift = shift;
+  for (int t = 0; t < nb; ++t) {
+    G.blocks[t] = L[t].block;
+    G.slots[t] = L[t].slot;
+    for (int l = 0; l < 3; ++l) G.kap[t][l] = L[t].kappa[l];
+    G.b[t] = b[t];
+    G.x[t] = x[t];
   }
   return ST_OK;
 }
@@ -256,22 +324,29 @@ int pcg_plain(pbr_ctx* c, int block, const double kappa[3], double shift, const 
 // launch of an iteration covers all of them, and a layout that has converged
 // drops out through its device flag.  Results per layout in iters[] / conv[];
 // returns ST_ENOCONV on a breakdown.
-int pcg_solve_batch(pbr_ctx* c, int nb, const int* blocks, const double kappa[3], double shift,
+int pcg_solve_batch(pbr_ctx* c, int nb, const LayoutRef* L, double shift,
                     const cplx* const* b, cplx* const* x, const pbr_opts& o, int* iters,
                     int* conv) {
-  for (int t = 0; t < nb; ++t) PBR_TRY(ensure_work(c, blocks[t]));
-  PcgScalars hs[5];
+  if (nb < 1 || nb > PBR_MAX_BATCH) {
+    c->set_error("batch of 1 to PBR_MAX_BATCH layouts expected");
+    return ST_EINVAL;
+  }
+  for (int t = 0; t < nb; ++t) PBR_TRY(ensure_work(c, L[t].slot, L[t].block));
+  PcgScalars hs[NSTATE];
   if (!o.precond) {
-    for (int t = 0; t < nb; ++t) PBR_TRY(pcg_plain(c, blocks[t], kappa, shift, b[t], x[t], o));
+    for (int t = 0; t < nb; ++t)
+      PBR_TRY(pcg_plain(c, L[t].slot, L[t].block, L[t].kappa, shift, b[t], x[t], o));
   } else {
     // fused iteration: matvec (+ (p, q) partials) and five preconditioner passes
     // that also update x, r and p and finish the CG scalars on the device
-    const Geo g = make_geo(c, blocks[0], kappa);
+    const Geo g = make_geo(c, L[0].block, L[0].kappa);
     PcgStep P[PBR_MAX_BATCH];
     ApplyLayout AL[PBR_MAX_BATCH];
     for (int t = 0; t < nb; ++t) {
-      LayoutWork& W = c->work[blocks[t] + 1];
-      P[t].block = blocks[t];
+      LayoutWork& W = c->wk(L[t].slot, L[t].block);
+      P[t].slot = L[t].slot;
+      P[t].block = L[t].block;
+      for (int l = 0; l < 3; ++l) P[t].kappa[l] = L[t].kappa[l];
       P[t].st = W.st;
       P[t].tol2 = o.tol_inner * o.tol_inner;
       P[t].x = x[t];
@@ -286,30 +361,41 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const int* blocks, const double kappa[3]
       P[t].part_rz = W.ppart + 2 * W.pcap;
       P[t].part_cap = W.pcap;
       P[t].init = 1;
-      AL[t].block = blocks[t];
+      const Geo gt = make_geo(c, L[t].block, L[t].kappa);
+      AL[t].block = L[t].block;
+      for (int l = 0; l < 3; ++l) AL[t].ph[l] = gt.ph[l];
       AL[t].x = W.p;
       AL[t].y = W.q;
       AL[t].st = W.st;
       AL[t].part = W.ppart;
     }
-    PBR_TRY(launch_pcg_precond_batch(c, kappa, nb, P, shift));
+    PBR_TRY(launch_pcg_precond_batch(c, nb, P, shift));
     for (int t = 0; t < nb; ++t) P[t].init = 0;
     const int chunk = o.check_every > 0 ? o.check_every : 10;
+    auto iterate = [&](int count) -> int {
+      for (int it = 0; it < count; ++it) {
+        int npq = 0;
+        PBR_TRY(launch_apply_batch(c, g, nb, AL, shift, P[0].part_cap, &npq));
+        for (int t = 0; t < nb; ++t) P[t].n_pq = npq;
+        PBR_TRY(launch_pcg_precond_batch(c, nb, P, shift));
+      }
+      return ST_OK;
+    };
     int done_iters = 0;
     for (;;) {
       const int todo = std::min(chunk, o.maxit_inner - done_iters);
       if (todo <= 0) break;
-      for (int it = 0; it < todo; ++it) {
-        int npq = 0;
-        PBR_TRY(launch_apply_batch(c, g, nb, AL, shift, P[0].part_cap, &npq));
-        for (int t = 0; t < nb; ++t) P[t].n_pq = npq;
-        PBR_TRY(launch_pcg_precond_batch(c, kappa, nb, P, shift));
-      }
+      if (o.graphs && todo == chunk && !c->graphs_broken)
+        PBR_TRY(ensure_pcg_graph(c, nb, L, b, x, shift, chunk, iterate));
+      if (o.graphs && todo == chunk && !c->graphs_broken)
+        PBR_HIP(c, hipGraphLaunch(c->pcg_graph.exec, c->stream));
+      else
+        PBR_TRY(iterate(todo));
       PBR_TRY(read_states(c, hs));
       bool all = true;
       done_iters = 0;
       for (int t = 0; t < nb; ++t) {
-        const PcgScalars& h = hs[blocks[t] + 1];
+        const PcgScalars& h = hs[state_index(L[t].slot, L[t].block)];
         done_iters = std::max(done_iters, h.iters);
         all = all && h.done;
       }
@@ -319,7 +405,7 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const int* blocks, const double kappa[3]
   PBR_TRY(read_states(c, hs));
   int status = ST_OK;
   for (int t = 0; t < nb; ++t) {
-    const PcgScalars& h = hs[blocks[t] + 1];
+    const PcgScalars& h = hs[state_index(L[t].slot, L[t].block)];
     iters[t] = h.iters;
     conv[t] = (h.done == 1) ? 1 : 0;
     if (h.done == 2) {
@@ -332,7 +418,10 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const int* blocks, const double kappa[3]
 
 int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b, cplx* x,
               const pbr_opts& o, int* iters, int* conv) {
-  return pcg_solve_batch(c, 1, &block, kappa, shift, &b, &x, o, iters, conv);
+  LayoutRef L;
+  L.block = block;
+  for (int l = 0; l < 3; ++l) L.kappa[l] = kappa[l];
+  return pcg_solve_batch(c, 1, &L, shift, &b, &x, o, iters, conv);
 }
 
 namespace {
@@ -345,7 +434,8 @@ struct OpCounters {
 // advance in lockstep: each step is one shift-invert application, done for all
 // active runs by one batched PCG.
 struct LanczosRun {
-  int block = -1, nev = 0, m = 0, ldh = 0;
+  int slot = 0, block = -1, nev = 0, m = 0, ldh = 0;
+  double kappa[3] = {0, 0, 0};
   bool gamma = false;
   long N = 0, n3 = 0, ld = 0;
   int n_zero = 0;
@@ -386,11 +476,14 @@ int lz_ritz(pbr_ctx* c, LanczosRun& R, int mm, double bl, const pbr_opts& o) {
   return ST_OK;
 }
 
-int lz_start(pbr_ctx* c, LanczosRun& R, int block, int nev, const double kappa[3],
-             const pbr_opts& o) {
+int lz_start(pbr_ctx* c, LanczosRun& R, const LayoutRef& L, int nev, const pbr_opts& o) {
   R.t0 = std::chrono::steady_clock::now();
-  PBR_TRY(ensure_work(c, block));
-  LayoutWork& W = c->work[block + 1];
+  const int block = L.block;
+  const double* kappa = L.kappa;
+  PBR_TRY(ensure_work(c, L.slot, block));
+  LayoutWork& W = c->wk(L.slot, block);
+  R.slot = L.slot;
+  for (int l = 0; l < 3; ++l) R.kappa[l] = kappa[l];
   R.block = block;
   R.nev = nev;
   R.N = W.N;
@@ -398,7 +491,7 @@ int lz_start(pbr_ctx* c, LanczosRun& R, int block, int nev, const double kappa[3
   R.ld = R.n3;
   R.gamma = is_gamma(kappa);
   if (R.gamma) {
-    PBR_TRY(ensure_null_fields(c, block));
+    PBR_TRY(ensure_null_fields(c, L.slot, block));
     R.n_zero = 3 * W.nf;
   }
   const long dim_eff = R.n3 - R.n_zero;
@@ -436,7 +529,7 @@ int lz_start(pbr_ctx* c, LanczosRun& R, int block, int nev, const double kappa[3
 // Continue run R after W.w = Op u_j: orthogonalise, extend H, test convergence,
 // restart when the basis is full.
 int lz_step(pbr_ctx* c, LanczosRun& R, const pbr_opts& o) {
-  LayoutWork& W = c->work[R.block + 1];
+  LayoutWork& W = c->wk(R.slot, R.block);
   const hipStream_t SO = c->stream;
   const int j = R.j;
   const long n3 = R.n3, ld = R.ld;
@@ -529,9 +622,9 @@ int lz_step(pbr_ctx* c, LanczosRun& R, const pbr_opts& o) {
 
 // Ritz vectors of the nev largest mu, final Rayleigh quotients and residuals
 // with the exact operator, eigenvalues ascending.
-int lz_finish(pbr_ctx* c, LanczosRun& R, const double kappa[3], double* evals, cplx* evecs_dev,
-              pbr_stats* st) {
-  LayoutWork& W = c->work[R.block + 1];
+int lz_finish(pbr_ctx* c, LanczosRun& R, double* evals, cplx* evecs_dev, pbr_stats* st) {
+  const double* kappa = R.kappa;
+  LayoutWork& W = c->wk(R.slot, R.block);
   DevMaterial& M = c->material(R.block);
   const hipStream_t SO = c->stream;
   const long N = R.N, n3 = R.n3, ld = R.ld;
@@ -618,23 +711,25 @@ int lz_finish(pbr_ctx* c, LanczosRun& R, const double kappa[3], double* evals, c
 
 // One shift-invert application w = M^{1/2} (A + shift M)^{-1} M^{1/2} u_j for
 // every active run, as one batched PCG.
-int op_apply_batch(pbr_ctx* c, const double kappa[3], double shift, const pbr_opts& o,
-                   LanczosRun* const* R, int na) {
-  int blocks[PBR_MAX_BATCH], its[PBR_MAX_BATCH], conv[PBR_MAX_BATCH];
+int op_apply_batch(pbr_ctx* c, double shift, const pbr_opts& o, LanczosRun* const* R, int na) {
+  LayoutRef L[PBR_MAX_BATCH];
+  int its[PBR_MAX_BATCH], conv[PBR_MAX_BATCH];
   const cplx* b[PBR_MAX_BATCH];
   cplx* x[PBR_MAX_BATCH];
   for (int t = 0; t < na; ++t) {
-    LayoutWork& W = c->work[R[t]->block + 1];
+    LayoutWork& W = c->wk(R[t]->slot, R[t]->block);
     const DevMaterial& M = c->material(R[t]->block);
-    blocks[t] = R[t]->block;
+    L[t].slot = R[t]->slot;
+    L[t].block = R[t]->block;
+    for (int l = 0; l < 3; ++l) L[t].kappa[l] = R[t]->kappa[l];
     PBR_TRY(vec_diag_scale(c, c->stream, W.N, M.srho, W.U + (long)R[t]->j * R[t]->ld, W.b));
     b[t] = W.b;
     x[t] = W.t;
   }
-  const int s = pcg_solve_batch(c, na, blocks, kappa, shift, b, x, o, its, conv);
+  const int s = pcg_solve_batch(c, na, L, shift, b, x, o, its, conv);
   if (s != ST_OK && s != ST_ENOCONV) return s;
   for (int t = 0; t < na; ++t) {
-    LayoutWork& W = c->work[R[t]->block + 1];
+    LayoutWork& W = c->wk(R[t]->slot, R[t]->block);
     const DevMaterial& M = c->material(R[t]->block);
     OpCounters& k = R[t]->cnt;
     k.applies += 1;
@@ -652,22 +747,26 @@ int op_apply_batch(pbr_ctx* c, const double kappa[3], double shift, const pbr_op
 // Lanczos runs for nb layouts of one kind in lockstep (one batched PCG per
 // step).  Per-layout results go to evals[t], evecs_dev[t] (may be null) and
 // st[t]; rc[t] is each run's status.  Returns the first hard error, else OK.
-int lanczos_batch(pbr_ctx* c, const double kappa[3], int nb, const int* blocks, const int* nev,
-                  double shift, const pbr_opts& o, double* const* evals,
-                  cplx* const* evecs_dev, pbr_stats* st, int* rc) {
-  LanczosRun R[PBR_MAX_BATCH];
-  for (int t = 0; t < nb; ++t) PBR_TRY(lz_start(c, R[t], blocks[t], nev[t], kappa, o));
+int lanczos_batch(pbr_ctx* c, int nb, const LayoutRef* L, const int* nev, double shift,
+                  const pbr_opts& o, double* const* evals, cplx* const* evecs_dev,
+                  pbr_stats* st, int* rc) {
+  if (nb < 1 || nb > PBR_MAX_BATCH) {
+    c->set_error("batch of 1 to PBR_MAX_BATCH layouts expected");
+    return ST_EINVAL;
+  }
+  std::vector<LanczosRun> R(nb);
+  for (int t = 0; t < nb; ++t) PBR_TRY(lz_start(c, R[t], L[t], nev[t], o));
   for (;;) {
     LanczosRun* act[PBR_MAX_BATCH];
     int na = 0;
     for (int t = 0; t < nb; ++t)
       if (!R[t].done) act[na++] = &R[t];
     if (!na) break;
-    PBR_TRY(op_apply_batch(c, kappa, shift, o, act, na));
+    PBR_TRY(op_apply_batch(c, shift, o, act, na));
     for (int t = 0; t < na; ++t) PBR_TRY(lz_step(c, *act[t], o));
   }
   for (int t = 0; t < nb; ++t) {
-    rc[t] = lz_finish(c, R[t], kappa, evals[t], evecs_dev ? evecs_dev[t] : nullptr,
+    rc[t] = lz_finish(c, R[t], evals[t], evecs_dev ? evecs_dev[t] : nullptr,
                       st ? &st[t] : nullptr);
     if (rc[t] != ST_OK && rc[t] != ST_ENOCONV) return rc[t];
   }
@@ -677,7 +776,10 @@ int lanczos_batch(pbr_ctx* c, const double kappa[3], int nb, const int* blocks, 
 int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double shift,
                  const pbr_opts& o, double* evals, cplx* evecs_dev, pbr_stats* st) {
   int rc = ST_OK;
-  PBR_TRY(lanczos_batch(c, kappa, 1, &block, &nev, shift, o, &evals, &evecs_dev, st, &rc));
+  LayoutRef L;
+  L.block = block;
+  for (int l = 0; l < 3; ++l) L.kappa[l] = kappa[l];
+  PBR_TRY(lanczos_batch(c, 1, &L, &nev, shift, o, &evals, &evecs_dev, st, &rc));
   return rc;
 }
 
@@ -695,82 +797,131 @@ void add_stats(pbr_stats* acc, const pbr_stats& one) {
   acc->pcg_avg = acc->op_applies ? (double)acc->pcg_iters_total / acc->op_applies : 0.0;
 }
 
-// Solve the blocks in `mask`: all in lockstep (one batched PCG per step), or
-// one after another with opts.concurrent = 0.
-int solve_blocks(pbr_ctx* c, const double kappa[3], int mask, const int nev_b[4], double shift,
-                 const pbr_opts& o, std::vector<double>* vals, pbr_stats* st) {
-  int blocks[4], nev[4], rc[4];
-  double* ev[4];
-  pbr_stats part[4];
-  std::memset(part, 0, sizeof(part));
-  int nb = 0;
-  for (int b = 0; b < 4; ++b) {
-    if (!(mask & (1 << b))) continue;
-    vals[b].assign(nev_b[b], 0.0);
-    blocks[nb] = b;
-    nev[nb] = nev_b[b];
-    ev[nb] = vals[b].data();
-    rc[nb] = ST_OK;
-    ++nb;
-  }
-  if (o.concurrent) {
-    PBR_TRY(lanczos_batch(c, kappa, nb, blocks, nev, shift, o, ev, nullptr, part, rc));
-  } else {
-    for (int t = 0; t < nb; ++t)
-      PBR_TRY(lanczos_batch(c, kappa, 1, blocks + t, nev + t, shift, o, ev + t, nullptr,
-                            part + t, rc + t));
-  }
+}  // namespace
+
+// Lowest nev eigenvalues of the full pencil at each of nk wave vectors from the
+// four blocks (Corollary 4.2): each block is asked for nev/4 + 4 values; a block
+// whose largest computed value lies below the merged nev-th value may hide
+// smaller ones that were not computed, so it is solved again with more values
+// until no block is flagged.  Up to PBR_KSLOTS k-points are solved at once, all
+// their pending (k, block) runs in lockstep (opts.concurrent; else one run after
+// another).  evals: nk x nev; stats summed over the k-points (nev_block of the
+// last one).
+int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
+                const pbr_opts& o, double* evals, pbr_stats* st) {
+  const long dimb = 3 * (c->n / 4);
   int status = ST_OK;
-  for (int t = 0; t < nb; ++t) {
-    if (st) add_stats(st, part[t]);
-    if (rc[t] == ST_ENOCONV) status = ST_ENOCONV;
+  int last_nev_b[4] = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < nk; k0 += PBR_KSLOTS) {
+    const int gk = std::min(PBR_KSLOTS, nk - k0);
+    int nev_b[PBR_KSLOTS][4], need[PBR_KSLOTS];
+    std::vector<double> vals[PBR_KSLOTS][4];
+    for (int q = 0; q < gk; ++q) {
+      const double* kap = kappas + 3 * (k0 + q);
+      const int nz = is_gamma(kap) ? 3 : 0;
+      for (int b = 0; b < 4; ++b)
+        nev_b[q][b] = (int)std::min<long>((nev + 3) / 4 + 4, dimb - nz - 1);
+      need[q] = 0xF;
+    }
+    for (int round = 0; round < 8; ++round) {
+      LayoutRef L[PBR_MAX_BATCH];
+      int nevs[PBR_MAX_BATCH], rc[PBR_MAX_BATCH], qk[PBR_MAX_BATCH];
+      double* ev[PBR_MAX_BATCH];
+      pbr_stats part[PBR_MAX_BATCH];
+      int np = 0;
+      for (int q = 0; q < gk; ++q)
+        for (int b = 0; b < 4; ++b) {
+          if (!(need[q] & (1 << b))) continue;
+          vals[q][b].assign(nev_b[q][b], 0.0);
+          L[np].slot = q;
+          L[np].block = b;
+          for (int l = 0; l < 3; ++l) L[np].kappa[l] = kappas[3 * (k0 + q) + l];
+          nevs[np] = nev_b[q][b];
+          ev[np] = vals[q][b].data();
+          qk[np] = q;
+          rc[np] = ST_OK;
+          ++np;
+        }
+      if (!np) break;
+      std::memset(part, 0, sizeof(part));
+      if (o.concurrent) {
+        PBR_TRY(lanczos_batch(c, np, L, nevs, shift, o, ev, nullptr, part, rc));
+      } else {
+        for (int t = 0; t < np; ++t)
+          PBR_TRY(lanczos_batch(c, 1, L + t, nevs + t, shift, o, ev + t, nullptr, part + t,
+                                rc + t));
+      }
+      for (int t = 0; t < np; ++t) {
+        if (st) add_stats(st, part[t]);
+        if (rc[t] == ST_ENOCONV) status = ST_ENOCONV;
+      }
+      (void)qk;
+      for (int q = 0; q < gk; ++q) {
+        const double* vp[4] = {vals[q][0].data(), vals[q][1].data(), vals[q][2].data(),
+                               vals[q][3].data()};
+        std::vector<double> merged(nev);
+        const int mask = pbr_host_merge(nev, nev_b[q], vp, merged.data());
+        if (mask < 0) {
+          c->set_error("block merge failed: fewer eigenvalues than requested");
+          return ST_EINVAL;
+        }
+        for (int t = 0; t < nev; ++t) evals[(long)(k0 + q) * nev + t] = merged[t];
+        const double* kap = kappas + 3 * (k0 + q);
+        const int nz = is_gamma(kap) ? 3 : 0;
+        need[q] = 0;
+        for (int b = 0; b < 4; ++b)
+          if (mask & (1 << b)) {
+            const int nb =
+                (int)std::min<long>(nev_b[q][b] + std::max(4, nev_b[q][b] / 2), dimb - nz - 1);
+            if (nb > nev_b[q][b]) {
+              nev_b[q][b] = nb;
+              need[q] |= 1 << b;
+            }
+          }
+      }
+    }
+    for (int b = 0; b < 4; ++b) last_nev_b[b] = nev_b[gk - 1][b];
+  }
+  if (st) {
+    for (int b = 0; b < 4; ++b) st->nev_block[b] = last_nev_b[b];
+    // Gamma null modes once per k-point (re-solved blocks are not counted twice)
+    st->n_zero = 0;
+    for (int q = 0; q < nk; ++q)
+      if (is_gamma(kappas + 3 * q)) st->n_zero += 12;
   }
   return status;
 }
 
-}  // namespace
-
-// Lowest nev eigenvalues of the full pencil from the four blocks (Corollary 4.2):
-// each block is asked for nev/4 + 4 values; a block whose largest computed value
-// lies below the merged nev-th value may hide smaller ones that were not computed,
-// so it is solved again with more values until no block is flagged.
 int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const pbr_opts& o,
                 double* evals, pbr_stats* st) {
-  int nev_b[4];
-  std::vector<double> vals[4];
-  const long dimb = 3 * (c->n / 4);
-  const int nz = is_gamma(kappa) ? 3 : 0;
-  auto cap = [&](int v) { return (int)std::min<long>(v, dimb - nz - 1); };
-  for (int b = 0; b < 4; ++b) nev_b[b] = cap((nev + 3) / 4 + 4);
-  int need = 0xF;
+  return merged_path(c, 1, kappa, nev, shift, o, evals, st);
+}
+
+// Full-space eigenvalues at nk wave vectors, up to PBR_KSLOTS in lockstep.
+int full_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
+              const pbr_opts& o, double* evals, pbr_stats* st) {
   int status = ST_OK;
-  for (int round = 0; round < 8 && need; ++round) {
-    const int s = solve_blocks(c, kappa, need, nev_b, shift, o, vals, st);
-    if (s == ST_ENOCONV)
-      status = ST_ENOCONV;
-    else if (s != ST_OK)
-      return s;
-    const double* vp[4] = {vals[0].data(), vals[1].data(), vals[2].data(), vals[3].data()};
-    std::vector<double> merged(nev);
-    const int mask = pbr_host_merge(nev, nev_b, vp, merged.data());
-    if (mask < 0) {
-      c->set_error("block merge failed: fewer eigenvalues than requested");
-      return ST_EINVAL;
+  const int group = o.concurrent ? PBR_KSLOTS : 1;
+  for (int k0 = 0; k0 < nk; k0 += group) {
+    const int gk = std::min(group, nk - k0);
+    LayoutRef L[PBR_KSLOTS];
+    int nevs[PBR_KSLOTS], rc[PBR_KSLOTS];
+    double* ev[PBR_KSLOTS];
+    pbr_stats part[PBR_KSLOTS];
+    std::memset(part, 0, sizeof(part));
+    for (int q = 0; q < gk; ++q) {
+      L[q].slot = q;
+      L[q].block = -1;
+      for (int l = 0; l < 3; ++l) L[q].kappa[l] = kappas[3 * (k0 + q) + l];
+      nevs[q] = nev;
+      ev[q] = evals + (long)(k0 + q) * nev;
+      rc[q] = ST_OK;
     }
-    for (int t = 0; t < nev; ++t) evals[t] = merged[t];
-    need = 0;
-    for (int b = 0; b < 4; ++b)
-      if (mask & (1 << b)) {
-        const int nb = cap(nev_b[b] + std::max(4, nev_b[b] / 2));
-        if (nb > nev_b[b]) {
-          nev_b[b] = nb;
-          need |= 1 << b;
-        }
-      }
-  }
-  if (st) {
-    for (int b = 0; b < 4; ++b) st->nev_block[b] = nev_b[b];
-    st->n_zero = 4 * nz;  // re-solved blocks are not counted twice
+    PBR_TRY(lanczos_batch(c, gk, L, nevs, shift, o, ev, nullptr, part, rc));
+    for (int q = 0; q < gk; ++q) {
+      if (st) add_stats(st, part[q]);
+      if (rc[q] == ST_ENOCONV) status = ST_ENOCONV;
+    }
   }
   return status;
 }

@@ -51,6 +51,7 @@ struct ApplyBlock {
   const PcgScalars* st;  // optional: this block's work-groups return once st->done != 0
   double* part;          // optional: per-work-group partials of Re(x^H y)
   int a, c;              // class bits of the block (unused in the natural layout)
+  cplx ph[3];            // e^{i phi_l} of this layout's wave vector
 };
 
 struct ApplyArgs {
@@ -222,6 +223,9 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   Geo g = A.g;
   g.a = P.a;
   g.c = P.c;
+  g.ph[0] = P.ph[0];
+  g.ph[1] = P.ph[1];
+  g.ph[2] = P.ph[2];
   const int L1 = g.L1, L2 = g.L2, L3 = g.L3;
   const int N = A.N;
   const __amdgpu_buffer_rsrc_t rx = rsrc(P.x, (unsigned)N * 48u);
@@ -465,7 +469,7 @@ constexpr int TILE_I = 16, TILE_J = 16;
 int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,
                        long part_cap, int* nparts) {
   if (nb < 1 || nb > PBR_MAX_BATCH) {
-    c->set_error("batch of 1 to 4 layouts expected");
+    c->set_error("batch of 1 to PBR_MAX_BATCH layouts expected");
     return ST_EINVAL;
   }
   const long Nl = c->layout_nodes(g.blocked ? 0 : -1);
@@ -500,6 +504,7 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
     B.part = L[t].part;
     B.a = L[t].block >= 0 ? L[t].block >> 1 : 0;
     B.c = L[t].block >= 0 ? L[t].block & 1 : 0;
+    for (int l = 0; l < 3; ++l) B.ph[l] = L[t].ph[l];
     if (B.part && A.per > part_cap) {
       c->set_error("grid too large for the PCG partial buffers");
       return ST_EINVAL;
@@ -516,6 +521,7 @@ int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, c
                  PcgScalars* st, double* part, long part_cap, int* nparts) {
   ApplyLayout L;
   L.block = block;
+  for (int l = 0; l < 3; ++l) L.ph[l] = g.ph[l];
   L.x = x;
   L.y = y;
   L.st = st;

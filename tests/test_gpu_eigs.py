@@ -155,3 +155,20 @@ def test_error_paths():
         ctx.eigs((0.1, 0.2, 0.3), -1, 3, opts=o)
     assert e.value.status == pbr.PBR_ENOCONV
     ctx.close()
+
+
+def test_merged_eigs_graphs_match_eager():
+    """The blocked path with captured PCG chunks gives the eager path's
+    eigenvalues bit for bit (n=16, three k-points in a row, graphs recaptured
+    per k)."""
+    dims = (16, 16, 16)
+    C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
+    ctx = make_ctx(dims, C21, rho)
+    ks, _ = sc_path(6)
+    out = {}
+    for graphs in (0, 1):
+        o = pbr.pbr_opts_default()
+        o.graphs = graphs
+        out[graphs] = ctx.band_path(ks[:3], 10, blocked=True, opts=o)[0]
+    assert np.array_equal(out[0], out[1])
+    ctx.close()
