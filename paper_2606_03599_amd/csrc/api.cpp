@@ -196,6 +196,8 @@ pbr_status pbr_create(pbr_ctx** out, int n1, int n2, int n3, const double* A_lat
       c->own_stream = (e == hipSuccess);
     }
   }
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount,
+                                               hip_device);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hpinned, sizeof(double) * PBR_PINNED);
   if (e != hipSuccess) {
     g_create_error = std::string("HIP device setup failed: ") + hipGetErrorString(e);
@@ -212,7 +214,7 @@ void pbr_destroy(pbr_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (auto& M : c->mat) {
-    dev_free(M.C);
+    dev_free(M.Ct);
     dev_free(M.rho);
     dev_free(M.srho);
     dev_free(M.isrho);

@@ -19,9 +19,20 @@
 #define PBR_PINNED 32768
 
 // Device material in one layout: C as 21 planes of N doubles (SoA), rho, sqrt(rho).
+// Stiffness as the stencil reads it: for every row (j, k) of the layout box and
+// every run of PBR_CT_W consecutive i, the 21 stiffness entries and rho of
+// those nodes, entry-major (22 x PBR_CT_W doubles, 2816 bytes, contiguous):
+//   Ct[(((k * L2 + j) * tiles + i / PBR_CT_W) * 22 + q) * PBR_CT_W + i % PBR_CT_W]
+// with tiles = ceil(L1 / PBR_CT_W), q < 21 the C21 entry, q = 21 rho; nodes past
+// L1 in the last run hold zeros.  One wave's loads of one entry for a 16 x 4
+// patch of nodes are then four 128-byte segments, and a row's 22 entries are
+// one contiguous 2.8 KB run of HBM.
+#define PBR_CT_W 16
+
 struct DevMaterial {
   long N = 0;
-  double* C = nullptr;      // [21][N]
+  long ct_len = 0;          // doubles in Ct
+  double* Ct = nullptr;     // stencil tiles (layout above)
   double* rho = nullptr;    // [N]
   double* srho = nullptr;   // [N]  sqrt(rho)
   double* isrho = nullptr;  // [N]  1/sqrt(rho)
@@ -65,6 +76,7 @@ struct pbr_ctx {
   double Ainv[9];      // row-major: Ainv[s*3+m] = (A_lat^-1)_{sm}
   double cf[3][5];     // Cartesian stencil coefficients
   int device = 0;
+  int cus = 256;       // compute units of the device
   hipStream_t stream = nullptr;
   bool own_stream = false;
 
@@ -155,6 +167,8 @@ struct ApplyLayout {
 // nb layouts of one kind (parity blocks, or natural layouts) in one launch;
 // g is the geometry of any of them (class bits and Bloch phases come from L[t]);
 // *nparts receives the partials per layout.
+// (x, y) partials one matvec launch writes per layout (block -1: natural)
+long apply_partials(const pbr_ctx* c, int block);
 int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,
                        long part_cap = 0, int* nparts = nullptr);
 int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,

@@ -70,14 +70,49 @@ MapArgs map_args(const pbr_ctx* c, int block) {
   return m;
 }
 
-int alloc_material(pbr_ctx* c, DevMaterial& M, long N) {
-  if (M.N == N && M.C) return ST_OK;
+// Interleave 21 stiffness planes and rho (layout order, box L1 x L2 x L3) into
+// the stencil's tiles; one thread per tile entry, padding written as zeros.
+__global__ void tile_kernel(int L1, int L2, int tiles, long len, long N,
+                            const double* __restrict__ C, const double* __restrict__ rho,
+                            double* __restrict__ Ct) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const int w = (int)(e % PBR_CT_W);
+  long r = e / PBR_CT_W;
+  const int q = (int)(r % 22);
+  r /= 22;
+  const int it = (int)(r % tiles);
+  r /= tiles;  // r = k * L2 + j
+  const int i = it * PBR_CT_W + w;
+  double v = 0.0;
+  if (i < L1) {
+    const long t = (long)i + (long)L1 * r;
+    v = q < 21 ? C[q * N + t] : rho[t];
+  }
+  Ct[e] = v;
+}
+
+int alloc_material(pbr_ctx* c, DevMaterial& M, long N, long ct_len) {
+  if (M.N == N && M.Ct) return ST_OK;
   M.N = N;
-  PBR_TRY(dev_alloc(c, (void**)&M.C, sizeof(double) * 21 * N));
+  M.ct_len = ct_len;
+  PBR_TRY(dev_alloc(c, (void**)&M.Ct, sizeof(double) * ct_len));
   PBR_TRY(dev_alloc(c, (void**)&M.rho, sizeof(double) * N));
   PBR_TRY(dev_alloc(c, (void**)&M.srho, sizeof(double) * N));
   PBR_TRY(dev_alloc(c, (void**)&M.isrho, sizeof(double) * N));
   return ST_OK;
+}
+
+// Tiles of one layout from its stiffness planes and rho.
+void launch_tile(pbr_ctx* c, int L1, int L2, int L3, const double* C, DevMaterial& M) {
+  const int tiles = (L1 + PBR_CT_W - 1) / PBR_CT_W;
+  const long len = (long)L3 * L2 * tiles * 22 * PBR_CT_W;
+  hipLaunchKernelGGL(tile_kernel, dim3((unsigned)ceil_div(len, 256)), dim3(256), 0, c->stream, L1,
+                     L2, tiles, len, M.N, C, (const double*)M.rho, M.Ct);
+}
+
+long tile_len(int L1, int L2, int L3) {
+  return (long)L3 * L2 * ((L1 + PBR_CT_W - 1) / PBR_CT_W) * 22 * PBR_CT_W;
 }
 
 }  // namespace
@@ -104,30 +139,45 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
   for (long x = 0; x < n; ++x)
     for (int q = 0; q < 21; ++q) planes[(size_t)q * n + x] = C21[(size_t)x * 21 + q];
   DevMaterial& F = c->mat[0];
-  PBR_TRY(alloc_material(c, F, n));
-  PBR_HIP(c, hipMemcpyAsync(F.C, planes.data(), sizeof(double) * 21 * n, hipMemcpyHostToDevice,
-                            c->stream));
-  PBR_HIP(c, hipMemcpyAsync(F.rho, rho, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL(sqrt_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream, n, F.rho,
-                     F.srho, F.isrho);
-  PBR_HIP(c, hipGetLastError());
-  if (c->even) {
-    for (int b = 0; b < 4; ++b) {
-      DevMaterial& B = c->mat[b + 1];
-      const long nb = n / 4;
-      PBR_TRY(alloc_material(c, B, nb));
-      MapArgs m = map_args(c, b);
-      hipLaunchKernelGGL(repack_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, m, 21,
-                         (const double*)F.C, B.C);
-      hipLaunchKernelGGL(repack_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, m, 1,
-                         (const double*)F.rho, B.rho);
-      hipLaunchKernelGGL(sqrt_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, nb, B.rho,
-                         B.srho, B.isrho);
-      PBR_HIP(c, hipGetLastError());
+  PBR_TRY(alloc_material(c, F, n, tile_len(c->n1, c->n2, c->n3)));
+  // natural planes (and one block's planes) live only during the upload
+  double* tmp = nullptr;
+  double* tmpb = nullptr;
+  int st = dev_alloc(c, (void**)&tmp, sizeof(double) * 21 * n);
+  if (st == ST_OK && c->even) st = dev_alloc(c, (void**)&tmpb, sizeof(double) * 21 * (n / 4));
+  auto run = [&]() -> int {
+    PBR_HIP(c, hipMemcpyAsync(tmp, planes.data(), sizeof(double) * 21 * n, hipMemcpyHostToDevice,
+                              c->stream));
+    PBR_HIP(c, hipMemcpyAsync(F.rho, rho, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(sqrt_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream, n, F.rho,
+                       F.srho, F.isrho);
+    launch_tile(c, c->n1, c->n2, c->n3, tmp, F);
+    PBR_HIP(c, hipGetLastError());
+    if (c->even) {
+      for (int b = 0; b < 4; ++b) {
+        DevMaterial& B = c->mat[b + 1];
+        const long nb = n / 4;
+        PBR_TRY(alloc_material(c, B, nb, tile_len(c->n1, c->n2 / 2, c->n3 / 2)));
+        MapArgs m = map_args(c, b);
+        hipLaunchKernelGGL(repack_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, m,
+                           21, (const double*)tmp, tmpb);
+        hipLaunchKernelGGL(repack_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, m, 1,
+                           (const double*)F.rho, B.rho);
+        hipLaunchKernelGGL(sqrt_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, nb,
+                           B.rho, B.srho, B.isrho);
+        launch_tile(c, c->n1, c->n2 / 2, c->n3 / 2, tmpb, B);
+        PBR_HIP(c, hipGetLastError());
+      }
     }
-  }
-  // the host staging vector dies at return: wait for the copies
-  PBR_HIP(c, hipStreamSynchronize(c->stream));
+    return ST_OK;
+  };
+  if (st == ST_OK) st = run();
+  // the host staging vector and the temporaries die here: wait for the work
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  dev_free(tmp);
+  dev_free(tmpb);
+  if (st != ST_OK) return st;
+  PBR_HIP(c, e);
   return ST_OK;
 }
 

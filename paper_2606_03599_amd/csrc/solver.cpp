@@ -203,7 +203,7 @@ int ensure_work(pbr_ctx* c, int slot, int block) {
   PBR_TRY(dev_alloc(c, (void**)&W.dscal, sizeof(double) * 4096));
   if (!c->st_all) PBR_TRY(dev_alloc(c, (void**)&c->st_all, sizeof(PcgScalars) * NSTATE));
   W.st = c->st_all + (5 * slot + block + 1);
-  W.pcap = N / 128 + 4096;
+  W.pcap = N / 128 + 4096 + apply_partials(c, block);
   PBR_TRY(dev_alloc(c, (void**)&W.ppart, sizeof(double) * 3 * W.pcap));
   return ST_OK;
 }

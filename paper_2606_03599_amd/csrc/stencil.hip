@@ -46,8 +46,7 @@ namespace {
 struct ApplyBlock {
   const cplx* x;
   cplx* y;
-  const double* C;
-  const double* rho;
+  const double* Ct;      // stiffness and rho tiles of the layout (DevMaterial::Ct)
   const PcgScalars* st;  // optional: this block's work-groups return once st->done != 0
   double* part;          // optional: per-work-group partials of Re(x^H y)
   int a, c;              // class bits of the block (unused in the natural layout)
@@ -57,6 +56,8 @@ struct ApplyBlock {
 struct ApplyArgs {
   Geo g;
   int N;              // nodes of one layout (all offsets below fit in 32 bits)
+  int ct_tiles;       // runs of PBR_CT_W nodes per row of the stiffness tiles
+  int ct_bytes;       // bytes of one layout's stiffness tiles
   double s;
   int tiles_i, tiles_j, chunk;
   int per;            // work-groups per layout
@@ -146,20 +147,9 @@ __device__ inline bool position_needed(const Geo& g, int TI, int TJ, int i0, int
   return need;
 }
 
-// Voigt stress from the velocity at the node (v0) and at its four backward
-// neighbours (vb), and the node's stiffness (upper triangle, row by row).
-__device__ inline void stress(const Geo& g, const cplx v0[3], const cplx vb[4][3],
-                              const double Cz[21], cplx tau[6]) {
-  cplx G[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      cplx acc = cscale(g.cf[m][0], v0[a]);
-#pragma unroll
-      for (int d = 1; d <= 4; ++d) acc = cfma(g.cf[m][d], vb[d - 1][a], acc);
-      G[m][a] = acc;
-    }
+// Voigt stress from the velocity gradient G[m][a] = (D'_m^H v_a) and the node's
+// stiffness (upper triangle, row by row).
+__device__ inline void stress_of_gradient(const cplx G[3][3], const double Cz[21], cplx tau[6]) {
   cplx eps[6];
   eps[0] = G[0][0];
   eps[1] = G[1][1];
@@ -191,21 +181,31 @@ __device__ inline void contrib(const Geo& g, const cplx* lds, int p, int d, cplx
   out[2] = cfma(c2, t2, cfma(c1, t3, cscale(c0, t4)));
 }
 
-__device__ inline int wslot(int v) { return ((v % 3) + 3) % 3; }
+__device__ inline int wslot(int v) { return v & 3; }
 
-// Work-group layout: TI*TJ "own" lanes (one output column each) followed by one
-// wave of ring lanes (the i+1 column and the j-1 / j+TJ rows of the tile).
+// Threads of a work-group for a TI x TJ tile: TI*TJ "own" lanes (one output
+// column each) followed by the ring lanes (the i+1 column and the j-1 / j+TJ
+// rows of the tile), rounded up to whole waves.
+__host__ __device__ constexpr int tile_threads(int TI, int TJ) {
+  return ((TI * TJ + (TJ + 2) + 2 * TI) + 63) / 64 * 64;
+}
+
+// Output planes per (x, y) partial of a tile; chunks are multiples of it.
+constexpr int PART_G = 4;
+
+// Work-group layout: own lanes, then ring lanes, then idle lanes up to a wave.
 template <int TI, int TJ>
-__global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A) {
+__global__ void __launch_bounds__(tile_threads(TI, TJ))
+    __attribute__((amdgpu_waves_per_eu(1, 1))) apply_stream_kernel(ApplyArgs A) {
   constexpr int PI = TI + 1, PJ = TJ + 2, NP = PI * PJ;  // tau region
   constexpr int XI = TI + 2, XJ = TJ + 4, NX = XI * XJ;  // velocity region
   constexpr int NOWN = TI * TJ;
-  constexpr int NT = NOWN + 64;
+  constexpr int NT = tile_threads(TI, TJ);
   constexpr int NH = PJ + 2 * TI;
   constexpr int XPASS = (NX + NT - 1) / NT;
-  static_assert(NH <= 64, "tau ring must fit in one wave");
+  static_assert(NOWN + NH <= NT, "own and ring lanes must fit the work-group");
   __shared__ cplx tau_s[6 * NP];
-  __shared__ cplx x_s[3][3 * NX];
+  __shared__ cplx x_s[4][3 * NX];
   __shared__ double red[NT / 64 + 1];
 
   // XCD-aware numbering: work-groups are dealt round-robin over 8 XCDs, so
@@ -230,9 +230,8 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   const int N = A.N;
   const __amdgpu_buffer_rsrc_t rx = rsrc(P.x, (unsigned)N * 48u);
   const __amdgpu_buffer_rsrc_t ry = rsrc(P.y, (unsigned)N * 48u);
-  const __amdgpu_buffer_rsrc_t rc = rsrc(P.C, (unsigned)N * 168u);
-  const __amdgpu_buffer_rsrc_t rr = rsrc(P.rho, (unsigned)N * 8u);
-  const int cs = N * 16, ds = N * 8;
+  const __amdgpu_buffer_rsrc_t rc = rsrc(P.Ct, (unsigned)A.ct_bytes);
+  const int cs = N * 16;
   const int ntile = A.tiles_i * A.tiles_j;
   const int tile = local % ntile;
   const int chunk = local / ntile;
@@ -256,7 +255,10 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
     xoff[r] = (p < NX) ? (ai + L1 * aj) * 16 : OOB;
     xph[r] = cmul(phase_pow(g.ph[0], qi), phase_pow(g.ph[1], qj));
   }
-  auto stage_load = [&](int v, cplx out[XPASS][3]) {
+  // loads of velocity plane v (none when !valid: the same instructions with
+  // out-of-range offsets, so the number of loads in flight never depends on
+  // the path taken)
+  auto stage_load = [&](int v, bool valid, cplx out[XPASS][3]) {
     int qk;
     const int kk = wrapq(v, L3, qk);
     const int kb = kk * L1 * L2 * 16;
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
     for (int r = 0; r < XPASS; ++r)
 #pragma unroll
       for (int a = 0; a < 3; ++a)
-        out[r][a] = ldc(rx, xoff[r] == OOB ? OOB : xoff[r] + kb, a * cs);
+        out[r][a] = ldc(rx, (xoff[r] == OOB || !valid) ? OOB : xoff[r] + kb, a * cs);
   };
   auto stage_store = [&](int v, cplx in[XPASS][3]) {
     int qk;
@@ -316,13 +318,15 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
     if (inbox_pos && s >= k0 && s < k1) return true;
     return position_needed(g, TI, TJ, i0, j0, iend, jend, k0, k1, ii, jj, s);
   };
-  auto load_C = [&](int s, bool need, double Cz[21], double& rz) {
+  // stiffness (21 entries) and rho of a tau plane into one register set
+  // (entry q of the node's run is q * PBR_CT_W doubles past entry 0)
+  const int ct_row = (ai / PBR_CT_W) * 22 * PBR_CT_W + ai % PBR_CT_W;
+  auto load_C = [&](int s, bool need, double Cz[22]) {
     int qk;
     const int kk = wrapq(s, L3, qk);
-    const int o8 = need ? (ai + L1 * (aj + L2 * kk)) * 8 : OOB;
+    const int o8 = need ? ((aj + L2 * kk) * A.ct_tiles * 22 * PBR_CT_W + ct_row) * 8 : OOB;
 #pragma unroll
-    for (int q = 0; q < 21; ++q) Cz[q] = ldd(rc, o8, q * ds);
-    rz = ldd(rr, o8, 0);
+    for (int q = 0; q < 22; ++q) Cz[q] = ldd(rc, o8, q * PBR_CT_W * 8);
   };
 
   // ---- output (own lanes) ----
@@ -338,133 +342,182 @@ __global__ void __launch_bounds__(TI * TJ + 64) apply_stream_kernel(ApplyArgs A)
   cplx A0[3], A1[3], A2[3];  // outputs of planes s-1, s, s+1
 #pragma unroll
   for (int a = 0; a < 3; ++a) A0[a] = A1[a] = A2[a] = mk(0, 0);
-  cplx xprev[3];
-  double rprev = 0.0;
-  double xy = 0.0;  // Re(x^H y) over this lane's outputs
-
-  // ---- prologue: velocity planes k0-2 .. k0, stiffness of tau plane k0-1 ----
-  {
-    cplx buf[XPASS][3];
-    for (int v = k0 - 2; v <= k0; ++v) {
-      stage_load(v, buf);
-      stage_store(v, buf);
+  // Re(x^H y) partials, one per tile and group of PART_G output planes,
+  // whatever the chunking (chunks are whole groups): each lane adds its terms
+  // of a group's planes in order; at the group's last plane the wave sums go to
+  // red[] and thread 0 finishes the partial at the top of the next step (after
+  // the barrier that ends it).  The later sum of the partials therefore does
+  // not depend on the chunk length or on how many layouts share the launch.
+  const bool want_part = P.part != nullptr;
+  double* const part_tile =
+      want_part ? P.part + (long)tile * ((L3 + PART_G - 1) / PART_G) : nullptr;
+  double xyl = 0.0;  // this lane's terms of the current group
+  int pend = -1;     // group whose wave sums sit in red[]
+  auto finish_part = [&]() {
+    if (want_part && pend >= 0 && tid == 0) {
+      double v = 0.0;
+      for (int w = 0; w < NT / 64; ++w) v += red[w];
+      part_tile[pend] = v;
     }
-  }
-  // velocity plane s+2 is stored at the top of step s from registers loaded one
-  // step earlier, so its loads have a whole step to arrive
+  };
 
-  bool need_cur = needed_at(k0 - 1);
-  double Ccur[21], rcur;
-  load_C(k0 - 1, need_cur, Ccur, rcur);
+  // ---- prologue: velocity planes k0-2 .. k0 staged, k0+1 in registers;
+  //      stiffness of tau planes k0-1 and k0 in flight ----
+  cplx XA[XPASS][3], XB[XPASS][3];
+  for (int v = k0 - 2; v <= k0; ++v) {
+    stage_load(v, true, XA);
+    stage_store(v, XA);
+  }
+  stage_load(k0 + 1, k0 + 1 <= k1 + 1, XB);
+  // Prefetch distances: the stiffness of plane s+2 is loaded right after the
+  // stress of plane s has consumed its registers (two sets alternate), and the
+  // velocity of plane s+3 is loaded at the top of step s and staged at the end
+  // of step s+1 (two register sets alternate), so every load has more than a
+  // whole step to arrive and no step waits for loads it issued itself.
+  bool need_a = needed_at(k0 - 1), need_b = needed_at(k0);
+  double Ca[22], Cb[22];
+  load_C(k0 - 1, need_a, Ca);
+  // keep the two sets in issue order: the loop's waits count on it
+  __builtin_amdgcn_sched_barrier(0);
+  load_C(k0, need_b, Cb);
+  const double shift = A.s;
   __syncthreads();
 
-  for (int s = k0 - 1; s <= k1; ++s) {
-    // issue the loads of the next stiffness plane and of velocity plane s+2
-    // ring slots: s-1, s, s+1 are read below; s+2 goes into the slot of s-2
-    cplx xnext[XPASS][3];
-    const bool more_x = s + 2 <= k1 + 1;
-    if (more_x) stage_load(s + 2, xnext);
-    const bool need_nxt = (s + 1 <= k1) && needed_at(s + 1);
-    double Cnxt[21], rnxt;
-    load_C(s + 1, need_nxt, Cnxt, rnxt);
-    // ---- tau of plane s from the staged velocity ----
-    const cplx* xs0 = x_s[wslot(s)];
-    // the shift term of output plane s-1 needs x(s-1) before its slot is reused
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xprev[a] = x_s[wslot(s - 1)][a * NX + xself];
-    if (need_cur) {
-      cplx v0[3], vb[4][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) v0[a] = xs0[a * NX + xself];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const cplx* xsd = x_s[wslot(s + dkn[d])];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) vb[d][a] = xsd[a * NX + xnb[d]];
-      }
-      cplx tau[6];
-      stress(g, v0, vb, Ccur, tau);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) tau_s[c * NP + pos] = tau[c];
-    }
-    __syncthreads();
-    // ---- consume plane s ----
-    if (out_ok) {
-      cplx c1[3], c3[3], gP[3], gM[3];
-      contrib<NP>(g, tau_s, pA, 1, c1);
-      contrib<NP>(g, tau_s, pB, 3, c3);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) gP[a] = cadd(c1[a], c3[a]);
-      contrib<NP>(g, tau_s, pA, 2, c1);
-      contrib<NP>(g, tau_s, pB, 4, c3);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) gM[a] = cadd(c1[a], c3[a]);
-      if (s >= k0 && s < k1) {
-        const cplx t0 = tau_s[0 * NP + pos], t5 = tau_s[5 * NP + pos];
-        const cplx t4 = tau_s[4 * NP + pos], t1 = tau_s[1 * NP + pos];
-        const cplx t3 = tau_s[3 * NP + pos], t2 = tau_s[2 * NP + pos];
-        const double a0 = g.cf[0][0], a1 = g.cf[1][0], a2 = g.cf[2][0];
-        A1[0] = cadd(A1[0], cfma(a2, t4, cfma(a1, t5, cscale(a0, t0))));
-        A1[1] = cadd(A1[1], cfma(a2, t3, cfma(a1, t1, cscale(a0, t5))));
-        A1[2] = cadd(A1[2], cfma(a2, t2, cfma(a1, t3, cscale(a0, t4))));
-      }
-      // forward steps with s3 = +1 / -1 reach plane s from output plane s - e3:
-      // natural layout e3 = s3; block layout e3 = 0 or w3.
-      if (!g.blocked) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          A0[a] = cadd(A0[a], gP[a]);
-          A2[a] = cadd(A2[a], gM[a]);
-        }
-      } else if (w3p) {  // w3 = +1: s3=+1 -> e3 = +1, s3=-1 -> e3 = 0
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          A0[a] = cadd(A0[a], gP[a]);
-          A1[a] = cadd(A1[a], gM[a]);
-        }
-      } else {  // w3 = -1: s3=+1 -> e3 = 0, s3=-1 -> e3 = -1
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          A1[a] = cadd(A1[a], gP[a]);
-          A2[a] = cadd(A2[a], gM[a]);
-        }
-      }
-      // ---- plane s-1 is complete: y = B C B^H x + shift rho x ----
-      const int t = s - 1;
-      if (t >= k0 && t < k1) {
-        const int o = io + L1 * (jo + L2 * t);
-        const double sr = A.s * rprev;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const cplx yv = cfma(sr, xprev[a], A0[a]);
-          stc(ry, yv, o * 16, a * cs);
-          xy = fma(xprev[a].x, yv.x, fma(xprev[a].y, yv.y, xy));
-        }
-      }
-    }
-    if (more_x) stage_store(s + 2, xnext);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      A0[a] = A1[a];
-      A1[a] = A2[a];
-      A2[a] = mk(0, 0);
-    }
-    rprev = rcur;
-#pragma unroll
-    for (int q = 0; q < 21; ++q) Ccur[q] = Cnxt[q];
-    rcur = rnxt;
-    need_cur = need_nxt;
-    __syncthreads();
+#define PBR_STEP(S_, Cuse, need_use, Xload, Xstore)                                   \
+  do {                                                                                \
+    const int s = (S_);                                                               \
+    finish_part();                                                                    \
+    stage_load(s + 3, s + 3 <= k1 + 1, Xload);                                        \
+    /* ---- tau of plane s from the staged velocity ---- */                           \
+    const cplx* xs0 = x_s[wslot(s)];                                                  \
+    if (need_use) {                                                                   \
+      /* velocity at the node and its four backward neighbours: all fifteen LDS */    \
+      /* reads are issued together, then the gradient G[m][a] = D'_m^H v_a; */        \
+      /* own nodes of an output plane also take the shift term s rho x here */        \
+      cplx v0[3], vb[4][3];                                                           \
+_Pragma("unroll")                                                                     \
+      for (int a = 0; a < 3; ++a) v0[a] = xs0[a * NX + xself];                        \
+_Pragma("unroll")                                                                     \
+      for (int d = 0; d < 4; ++d) {                                                   \
+        const cplx* xsd = x_s[wslot(s + dkn[d])];                                     \
+_Pragma("unroll")                                                                     \
+        for (int a = 0; a < 3; ++a) vb[d][a] = xsd[a * NX + xnb[d]];                  \
+      }                                                                               \
+      if (out_ok && s >= k0 && s < k1) {                                              \
+        const double sr = shift * Cuse[21];                                           \
+_Pragma("unroll")                                                                     \
+        for (int a = 0; a < 3; ++a) A1[a] = cfma(sr, v0[a], A1[a]);                   \
+      }                                                                               \
+      cplx G[3][3];                                                                   \
+_Pragma("unroll")                                                                     \
+      for (int a = 0; a < 3; ++a)                                                     \
+_Pragma("unroll")                                                                     \
+        for (int m = 0; m < 3; ++m) {                                                 \
+          cplx acc = cscale(g.cf[m][0], v0[a]);                                       \
+_Pragma("unroll")                                                                     \
+          for (int d = 1; d <= 4; ++d) acc = cfma(g.cf[m][d], vb[d - 1][a], acc);     \
+          G[m][a] = acc;                                                              \
+        }                                                                             \
+      cplx tau[6];                                                                    \
+      stress_of_gradient(G, Cuse, tau);                                               \
+_Pragma("unroll")                                                                     \
+      for (int c = 0; c < 6; ++c) tau_s[c * NP + pos] = tau[c];                       \
+    }                                                                                 \
+    /* stiffness of plane s+2 into the registers just consumed */                    \
+    need_use = (s + 2 <= k1) && needed_at(s + 2);                                     \
+    load_C(s + 2, need_use, Cuse);                                                    \
+    __syncthreads();                                                                  \
+    /* ---- consume plane s ---- */                                                   \
+    const int t = s - 1; /* output plane completed in this step */                    \
+    if (out_ok) {                                                                     \
+      cplx c1[3], c3[3], gP[3], gM[3];                                                \
+      contrib<NP>(g, tau_s, pA, 1, c1);                                               \
+      contrib<NP>(g, tau_s, pB, 3, c3);                                               \
+_Pragma("unroll")                                                                     \
+      for (int a = 0; a < 3; ++a) gP[a] = cadd(c1[a], c3[a]);                         \
+      contrib<NP>(g, tau_s, pA, 2, c1);                                               \
+      contrib<NP>(g, tau_s, pB, 4, c3);                                               \
+_Pragma("unroll")                                                                     \
+      for (int a = 0; a < 3; ++a) gM[a] = cadd(c1[a], c3[a]);                         \
+      if (s >= k0 && s < k1) {                                                        \
+        const cplx t0 = tau_s[0 * NP + pos], t5 = tau_s[5 * NP + pos];                \
+        const cplx t4 = tau_s[4 * NP + pos], t1 = tau_s[1 * NP + pos];                \
+        const cplx t3 = tau_s[3 * NP + pos], t2 = tau_s[2 * NP + pos];                \
+        const double a0 = g.cf[0][0], a1 = g.cf[1][0], a2 = g.cf[2][0];               \
+        A1[0] = cadd(A1[0], cfma(a2, t4, cfma(a1, t5, cscale(a0, t0))));              \
+        A1[1] = cadd(A1[1], cfma(a2, t3, cfma(a1, t1, cscale(a0, t5))));              \
+        A1[2] = cadd(A1[2], cfma(a2, t2, cfma(a1, t3, cscale(a0, t4))));              \
+      }                                                                               \
+      /* forward steps with s3 = +1 / -1 reach plane s from output plane s - e3: */   \
+      /* natural layout e3 = s3; block layout e3 = 0 or w3. */                        \
+      if (!g.blocked) {                                                               \
+_Pragma("unroll")                                                                     \
+        for (int a = 0; a < 3; ++a) {                                                 \
+          A0[a] = cadd(A0[a], gP[a]);                                                 \
+          A2[a] = cadd(A2[a], gM[a]);                                                 \
+        }                                                                             \
+      } else if (w3p) { /* w3 = +1: s3=+1 -> e3 = +1, s3=-1 -> e3 = 0 */              \
+_Pragma("unroll")                                                                     \
+        for (int a = 0; a < 3; ++a) {                                                 \
+          A0[a] = cadd(A0[a], gP[a]);                                                 \
+          A1[a] = cadd(A1[a], gM[a]);                                                 \
+        }                                                                             \
+      } else { /* w3 = -1: s3=+1 -> e3 = 0, s3=-1 -> e3 = -1 */                       \
+_Pragma("unroll")                                                                     \
+        for (int a = 0; a < 3; ++a) {                                                 \
+          A1[a] = cadd(A1[a], gP[a]);                                                 \
+          A2[a] = cadd(A2[a], gM[a]);                                                 \
+        }                                                                             \
+      }                                                                               \
+      /* ---- plane s-1 is complete: y = B C B^H x + shift rho x ---- */              \
+      if (t >= k0 && t < k1) {                                                        \
+        const int o = io + L1 * (jo + L2 * t);                                        \
+        cplx xprev[3];                                                                \
+_Pragma("unroll")                                                                     \
+        for (int a = 0; a < 3; ++a) xprev[a] = x_s[wslot(t)][a * NX + xself];         \
+_Pragma("unroll")                                                                     \
+        for (int a = 0; a < 3; ++a) {                                                 \
+          const cplx yv = A0[a];                                                      \
+          stc(ry, yv, o * 16, a * cs);                                                \
+          xyl = fma(xprev[a].x, yv.x, fma(xprev[a].y, yv.y, xyl));                    \
+        }                                                                             \
+      }                                                                               \
+    }                                                                                 \
+    pend = -1;                                                                        \
+    if (want_part && t >= k0 && t < k1 && (t % PART_G == PART_G - 1 || t == L3 - 1)) {\
+      const double wsum = wave_sum(xyl);                                              \
+      if ((tid & 63) == 0) red[tid >> 6] = wsum;                                      \
+      xyl = 0.0;                                                                      \
+      pend = t / PART_G;                                                              \
+    }                                                                                 \
+    /* velocity plane s+2 (loaded a step ago) into the slot of plane s-2 */           \
+    if (s + 2 <= k1 + 1) stage_store(s + 2, Xstore);                                  \
+_Pragma("unroll")                                                                     \
+    for (int a = 0; a < 3; ++a) {                                                     \
+      A0[a] = A1[a];                                                                  \
+      A1[a] = A2[a];                                                                  \
+      A2[a] = mk(0, 0);                                                               \
+    }                                                                                 \
+    __syncthreads();                                                                  \
+  } while (0)
+
+  for (int s0 = k0 - 1; s0 <= k1; s0 += 2) {
+    PBR_STEP(s0, Ca, need_a, XA, XB);
+    if (s0 + 1 <= k1) PBR_STEP(s0 + 1, Cb, need_b, XB, XA);
   }
-  if (P.part) {
-    const double v = block_sum_all(xy, red);
-    if (tid == 0) P.part[local] = v;
-  }
+#undef PBR_STEP
+  finish_part();
 }
 
-constexpr int TILE_I = 16, TILE_J = 16;
+constexpr int TILE_I = 16, TILE_J = 13;
 
 }  // namespace
+
+long apply_partials(const pbr_ctx* c, int block) {
+  const long L1 = c->n1, L2 = block < 0 ? c->n2 : c->n2 / 2, L3 = block < 0 ? c->n3 : c->n3 / 2;
+  return ((L1 + TILE_I - 1) / TILE_I) * ((L2 + TILE_J - 1) / TILE_J) *
+         ((L3 + PART_G - 1) / PART_G);
+}
 
 int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,
                        long part_cap, int* nparts) {
@@ -473,46 +526,63 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
     return ST_EINVAL;
   }
   const long Nl = c->layout_nodes(g.blocked ? 0 : -1);
-  if (Nl * 168L >= (1L << 31)) {
+  const int ct_tiles = (g.L1 + PBR_CT_W - 1) / PBR_CT_W;
+  const long ct_len = (long)g.L3 * g.L2 * ct_tiles * 22 * PBR_CT_W;
+  if (Nl * 48L >= (1L << 31) || ct_len * 8L >= (1L << 31)) {
     c->set_error("grid too large for 32-bit buffer offsets of the stencil kernel");
     return ST_EINVAL;
   }
   ApplyArgs A;
   A.g = g;
   A.N = (int)Nl;
+  A.ct_tiles = ct_tiles;
+  A.ct_bytes = (int)(ct_len * 8);
   A.s = s;
   A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
   A.tiles_j = (g.L2 + TILE_J - 1) / TILE_J;
-  // chunk length: about one work-group per CU (256 CUs) for one layout; longer
-  // chunks amortise the two partial planes a chunk stages at its ends
+  // chunk length: one work-group fits a CU at a time (LDS and registers), so
+  // a launch runs in ceil(work-groups / CUs) rounds, each as long as its
+  // longest chunk plus its start-up (the two partial planes a chunk computes at
+  // its ends and the first loads, which nothing overlaps): pick the chunk that
+  // minimises rounds x (chunk + 4) for this batch among whole groups of
+  // PART_G planes (or the whole box), so no result depends on the choice.
   const long tiles = (long)A.tiles_i * A.tiles_j;
-  int chunk = (int)std::max<long>(1, (tiles * g.L3) / 256);
-  chunk = std::max(chunk, 4);
-  chunk = std::min(chunk, g.L3);
+  const int cus = std::max(1, c->cus);
+  int chunk = g.L3;
+  long best = -1;
+  for (int ch = std::min(PART_G, g.L3); ch <= g.L3; ++ch) {
+    if (ch % PART_G != 0 && ch != g.L3) continue;
+    const long wgs = (long)nb * tiles * ((g.L3 + ch - 1) / ch);
+    const long cost = ((wgs + cus - 1) / cus) * (ch + 4);
+    if (best < 0 || cost < best) {
+      best = cost;
+      chunk = ch;
+    }
+  }
   A.chunk = chunk;
   const int nchunks = (g.L3 + chunk - 1) / chunk;
   A.per = (int)(tiles * nchunks);
-  if (nparts) *nparts = A.per;
+  const long np = tiles * ((g.L3 + PART_G - 1) / PART_G);  // (x, y) partials per layout
+  if (nparts) *nparts = (int)np;
   for (int t = 0; t < nb; ++t) {
     const DevMaterial& M = c->material(L[t].block);
     ApplyBlock& B = A.b[t];
     B.x = L[t].x;
     B.y = L[t].y;
-    B.C = M.C;
-    B.rho = M.rho;
+    B.Ct = M.Ct;
     B.st = L[t].st;
     B.part = L[t].part;
     B.a = L[t].block >= 0 ? L[t].block >> 1 : 0;
     B.c = L[t].block >= 0 ? L[t].block & 1 : 0;
     for (int l = 0; l < 3; ++l) B.ph[l] = L[t].ph[l];
-    if (B.part && A.per > part_cap) {
+    if (B.part && np > part_cap) {
       c->set_error("grid too large for the PCG partial buffers");
       return ST_EINVAL;
     }
   }
   const unsigned grid = (unsigned)((long)A.per * nb);
   hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
-                     dim3(TILE_I * TILE_J + 64), 0, c->stream, A);
+                     dim3(tile_threads(TILE_I, TILE_J)), 0, c->stream, A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
