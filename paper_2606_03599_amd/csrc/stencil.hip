@@ -191,7 +191,7 @@ __host__ __device__ constexpr int tile_threads(int TI, int TJ) {
 }
 
 // Output planes per (x, y) partial of a tile; chunks are multiples of it.
-constexpr int PART_G = 4;
+constexpr int PART_G = 2;
 
 // Work-group layout: own lanes, then ring lanes, then idle lanes up to a wave.
 template <int TI, int TJ>
