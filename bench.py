@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=0)
-    p.add_argument("--study", choices=("refinement",), default=None,
+    p.add_argument("--study", choices=("refinement", "cells"), default=None,
                    help="refinement: grid-refinement errors of the FCC workload at X, W and L "
                         "against a 256^3 blocked reference (one JSON line)")
     p.add_argument("--workload", choices=("cube", "fcc"), default="cube",
@@ -214,6 +214,51 @@ def refinement_study(grids=(16, 32, 64, 128), ref=256, nev=8, points=("X", "W", 
             "observed_order": order, "seconds": round(time.perf_counter() - t0, 1)}
 
 
+def cells_study(nk, nev, count=8, seed=0):
+    """Uneven batch of two-phase cells (n drawn from {64, 96, 128}, inclusion
+    radius from U[0.2, 0.4], each with its own seeded inclusion stiffness): the
+    blocked band paths of all cells one after another, then all cells at once
+    (pbr_band_paths: one host thread and stream per cell).  Results must agree
+    bit for bit."""
+    import numpy as np
+    import torch
+    from paper_2606_03599_amd import pbr
+    from synth import batch_cells, sc_path
+    cells = batch_cells(count, seed=seed)
+    kappas, _ = sc_path(nk)
+    ctxs = []
+    for n, r, C21, rho in cells:
+        ctx = pbr.Context((n, n, n))
+        ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
+        ctxs.append(ctx)
+    sizes = [c[0] for c in cells]
+    radii = [round(c[1], 4) for c in cells]
+    del cells
+    log(f"cells: n = {sizes}, radius = {radii}, {nk} k-points, nev = {nev}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    serial = []
+    for q, ctx in enumerate(ctxs):
+        serial.append(ctx.band_path(kappas, nev)[0])
+        log(f"cell {q} (n={sizes[q]}) one after another: {time.perf_counter() - t0:.1f} s")
+    t_serial = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    conc, sts = pbr.band_paths(ctxs, [kappas] * len(ctxs), nev)
+    t_conc = time.perf_counter() - t0
+    log(f"all cells at once: {t_conc:.1f} s (one after another {t_serial:.1f} s)")
+    same = all(np.array_equal(a, b) for a, b in zip(serial, conc))
+    for ctx in ctxs:
+        ctx.close()
+    return {"study": "uneven batch of cells, blocked band paths, one after another vs all cells "
+                     "at once (pbr_band_paths)",
+            "cells": [{"n": n, "radius": r} for n, r in zip(sizes, radii)],
+            "k_points": nk, "nev": nev,
+            "one_after_another_s": round(t_serial, 3), "concurrent_s": round(t_conc, 3),
+            "speedup": round(t_serial / t_conc, 3),
+            "solves": int(sum(s.op_applies for s in sts)),
+            "results_identical": bool(same)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -222,6 +267,10 @@ def main():
         sys.exit(2)
     if args.study == "refinement":
         print(json.dumps(refinement_study()), flush=True)
+        return
+    if args.study == "cells":
+        print(json.dumps(cells_study(args.nk if args.nk != 16 else 6,
+                                     args.nev if args.nev > 0 else 16)), flush=True)
         return
     import numpy as np
     import torch

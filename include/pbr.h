@@ -210,6 +210,23 @@ pbr_status pbr_band_path(pbr_ctx *c, int nk, const double *kappas, int nev,
                          int blocked, double shift, const pbr_opts *opts,
                          double *evals, pbr_stats *st);
 
+/* Band structures of several unit cells at once, each with its own grid,
+ * lattice and material (one context per cell; the method is the per-cell one of
+ * pbr_band_path, Sec. 6.1).  Cell q is ctxs[q] with nk[q] reduced wave vectors
+ * kappas[q] (nk[q] x 3, host, row-major) and results evals[q] (nk[q] x nev,
+ * host); shift <= 0 takes each cell's default.  The cells' paths run
+ * concurrently, one native host thread per cell driving its context's own
+ * stream, so that small cells fill the GPU together; every cell's eigenvalues
+ * are bit for bit those of pbr_band_path on it.  The contexts must be distinct,
+ * on one device, and must not share a stream; 1 <= ncells <= 64.  st (optional)
+ * receives ncells statistics.  Returns PBR_OK, or the first failing cell's
+ * status (its message via pbr_last_error on that context; every cell is run);
+ * PBR_EINVAL for bad arguments before any cell starts. */
+pbr_status pbr_band_paths(int ncells, pbr_ctx *const *ctxs, const int *nk,
+                          const double *const *kappas, int nev, int blocked,
+                          double shift, const pbr_opts *opts, double *const *evals,
+                          pbr_stats *st);
+
 /* Derivatives of eigenvalues with respect to the material (first-order
  * perturbation of the pencil of Eq. 3.15): for nvec eigenpairs (lambda[s], v_s)
  * of layout `block` at kappa, with v_s^H M v_s = 1 as pbr_eigs returns them,

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pbr.h"
@@ -644,6 +645,42 @@ pbr_status pbr_band_path(pbr_ctx* c, int nk, const double* kappas, int nev, int 
   acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = acc;
   return (pbr_status)st;
+}
+
+pbr_status pbr_band_paths(int ncells, pbr_ctx* const* ctxs, const int* nk,
+                          const double* const* kappas, int nev, int blocked, double shift,
+                          const pbr_opts* opts, double* const* evals, pbr_stats* stats) {
+  if (ncells < 1 || ncells > 64 || !ctxs || !nk || !kappas || !evals) return PBR_EINVAL;
+  for (int q = 0; q < ncells; ++q) {
+    if (!ctxs[q] || nk[q] < 1 || !kappas[q] || !evals[q]) return PBR_EINVAL;
+    for (int r = 0; r < q; ++r) {
+      if (ctxs[r] == ctxs[q] || ctxs[r]->stream == ctxs[q]->stream ||
+          ctxs[r]->device != ctxs[q]->device) {
+        ctxs[q]->set_error("contexts of pbr_band_paths must be distinct, on one device, "
+                           "with their own streams");
+        return PBR_EINVAL;
+      }
+    }
+  }
+  std::vector<pbr_status> res(ncells, PBR_OK);
+  std::vector<pbr_stats> acc(ncells);
+  auto run = [&](int q) {
+    res[q] = pbr_band_path(ctxs[q], nk[q], kappas[q], nev, blocked, shift, opts, evals[q],
+                           &acc[q]);
+  };
+  if (ncells == 1) {
+    run(0);
+  } else {
+    std::vector<std::thread> th;
+    th.reserve(ncells);
+    for (int q = 0; q < ncells; ++q) th.emplace_back(run, q);
+    for (auto& t : th) t.join();
+  }
+  if (stats)
+    for (int q = 0; q < ncells; ++q) stats[q] = acc[q];
+  for (int q = 0; q < ncells; ++q)
+    if (res[q] != PBR_OK) return res[q];
+  return PBR_OK;
 }
 
 }  // extern "C"

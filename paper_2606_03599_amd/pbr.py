@@ -89,6 +89,11 @@ _SIGS = {
     "pbr_band_path": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.POINTER(PbrOpts), _dp,
                                      ctypes.POINTER(PbrStats)]),
+    "pbr_band_paths": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_dp),
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.POINTER(PbrOpts), ctypes.POINTER(_dp),
+                                      ctypes.POINTER(PbrStats)]),
     "pbr_last_error": (ctypes.c_char_p, [_vp]),
     "pbr_destroy": (None, [_vp]),
     "pbr_host_heev": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp]),
@@ -306,6 +311,32 @@ def pbr_band_path(ctx, kappas, nev, blocked=True, shift=0.0, opts=None, raise_on
     return ev, st
 
 
+def pbr_band_paths(ctxs, kappas_list, nev, blocked=True, shift=0.0, opts=None,
+                   raise_on_noconv=True):
+    """Band paths of several cells concurrently (one context per cell); returns
+    ([evals per cell], [PbrStats per cell])."""
+    ncells = len(ctxs)
+    ks = [np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1, 3))
+          for k in kappas_list]
+    evs = [np.zeros((k.shape[0], int(nev))) for k in ks]
+    hs = (_vp * ncells)(*[c if isinstance(c, int) else c.value for c in ctxs])
+    nks = (ctypes.c_int * ncells)(*[k.shape[0] for k in ks])
+    kp = (_dp * ncells)(*[k.ctypes.data_as(_dp) for k in ks])
+    ep = (_dp * ncells)(*[e.ctypes.data_as(_dp) for e in evs])
+    sts = (PbrStats * ncells)()
+    o = opts if opts is not None else pbr_opts_default()
+    status = lib().pbr_band_paths(ncells, hs, nks, kp, int(nev), 1 if blocked else 0,
+                                  float(shift), ctypes.byref(o), ep, sts)
+    if status != PBR_OK and (status != PBR_ENOCONV or raise_on_noconv):
+        bad = None
+        for c in ctxs:
+            if lib().pbr_last_error(c):
+                bad = c
+                break
+        _check(bad, status)
+    return evs, list(sts)
+
+
 def pbr_host_heev(A):
     A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128).T)  # column-major
     m = A.shape[0]
@@ -325,6 +356,11 @@ def pbr_host_merge(nev, block_vals):
     out = np.zeros(int(nev))
     mask = lib().pbr_host_merge(int(nev), nb, ptrs, out.ctypes.data_as(_dp))
     return mask, out
+
+
+def band_paths(contexts, kappas_list, nev, blocked=True, shift=0.0, opts=None):
+    """pbr_band_paths over Context objects: cells of their own sizes, concurrently."""
+    return pbr_band_paths([c.h for c in contexts], kappas_list, nev, blocked, shift, opts)
 
 
 class Context:

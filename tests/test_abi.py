@@ -3,6 +3,7 @@ headers declare, and its host-side logic (Rayleigh-Ritz eigensolver, merge
 certification, argument validation that fails before touching a device) works.
 """
 
+import ctypes
 import os
 import re
 
@@ -61,6 +62,17 @@ def test_null_context_calls_fail_cleanly(L):
     assert L.pbr_block_dim(None, 0) == -1
     assert L.pbr_default_shift(None) < 0
     L.pbr_destroy(None)
+
+
+def test_band_paths_rejects_bad_arguments(L):
+    """pbr_band_paths validates its arguments before any cell starts (no GPU)."""
+    from paper_2606_03599_amd import pbr
+    L.pbr_band_paths.restype = ctypes.c_int
+    assert L.pbr_band_paths(0, None, None, None, 4, 1, 0.0, None, None, None) == pbr.PBR_EINVAL
+    assert L.pbr_band_paths(65, None, None, None, 4, 1, 0.0, None, None, None) == pbr.PBR_EINVAL
+    hs = (ctypes.c_void_p * 2)(None, None)
+    nk = (ctypes.c_int * 2)(1, 1)
+    assert L.pbr_band_paths(2, hs, nk, None, 4, 1, 0.0, None, None, None) == pbr.PBR_EINVAL
 
 
 @pytest.mark.parametrize("m", [1, 2, 5, 17, 40])
