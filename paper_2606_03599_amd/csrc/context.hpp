@@ -17,6 +17,7 @@
 #define PBR_MAX_BATCH (4 * PBR_KSLOTS)
 // Doubles of pinned host scratch per context.
 #define PBR_PINNED 32768
+#define PBR_TUNE_SLOTS 16
 
 // Device material in one layout: C as 21 planes of N doubles (SoA), rho, sqrt(rho).
 // Stiffness as the stencil reads it: for every row (j, k) of the layout box and
@@ -77,6 +78,11 @@ struct pbr_ctx {
   double cf[3][5];     // Cartesian stencil coefficients
   int device = 0;
   int cus = 256;       // compute units of the device
+  // stencil chunk lengths chosen by the autotuner, per (batch size, box)
+  struct StencilTune {
+    int nb = 0, L1 = 0, L2 = 0, L3 = 0, chunk = 0;
+  } stencil_tune[PBR_TUNE_SLOTS];
+  int stencil_tune_next = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
 
@@ -167,6 +173,8 @@ struct ApplyLayout {
 // nb layouts of one kind (parity blocks, or natural layouts) in one launch;
 // g is the geometry of any of them (class bits and Bloch phases come from L[t]);
 // *nparts receives the partials per layout.
+// whether the stencil's work split for this batch size and box is tuned already
+bool apply_tuned(const pbr_ctx* c, const Geo& g, int nb);
 // (x, y) partials one matvec launch writes per layout (block -1: natural)
 long apply_partials(const pbr_ctx* c, int block);
 int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,

@@ -381,6 +381,12 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const LayoutRef* L, double shift,
       }
       return ST_OK;
     };
+    // let the stencil's autotuner see this batch before a graph freezes the
+    // launch (q = A p of the initial p; the first iteration recomputes it)
+    if (o.graphs && !c->graphs_broken && !apply_tuned(c, g, nb)) {
+      int npq = 0;
+      PBR_TRY(launch_apply_batch(c, g, nb, AL, shift, P[0].part_cap, &npq));
+    }
     int done_iters = 0;
     for (;;) {
       const int todo = std::min(chunk, o.maxit_inner - done_iters);

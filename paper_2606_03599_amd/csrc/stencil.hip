@@ -35,6 +35,9 @@
 //    ring re-reads of C and x in that XCD's L2;
 //  * all global accesses are buffer loads/stores with 32-bit offsets (one
 //    descriptor per array, scalar plane offsets).
+#include <algorithm>
+#include <vector>
+
 #include "blas.hpp"
 #include "context.hpp"
 #include "reduce.hpp"
@@ -513,6 +516,77 @@ constexpr int TILE_I = 16, TILE_J = 13;
 
 }  // namespace
 
+// Chunk length of a launch.  One work-group fits a CU at a time (LDS and
+// registers), so a launch runs in ceil(work-groups / CUs) rounds, each as long
+// as its longest chunk plus its start-up (the two partial planes a chunk
+// computes at its ends and the first loads, which nothing overlaps); the model
+// cost rounds x (chunk + 4) ranks the chunk lengths that are whole groups of
+// PART_G planes (or the whole box).  The autotuner times the four best of
+// them with real launches the first time a (batch size, box) is seen outside
+// stream capture, and keeps the fastest in the context; during capture, or
+// when timing fails, the model's best is used.  The launches are the caller's
+// own (same inputs, same outputs, rewritten), and since the (x, y) partials are
+// per tile and group no result depends on which chunk wins.
+template <class F>
+int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, long tiles, F&& launch, int* out) {
+  for (const auto& e : c->stencil_tune)
+    if (e.nb == nb && e.L1 == g.L1 && e.L2 == g.L2 && e.L3 == g.L3 && e.chunk > 0) {
+      *out = e.chunk;
+      return ST_OK;
+    }
+  const int cus = std::max(1, c->cus);
+  std::vector<std::pair<long, int>> cand;  // (model cost, chunk)
+  for (int ch = std::min(PART_G, g.L3); ch <= g.L3; ++ch) {
+    if (ch % PART_G != 0 && ch != g.L3) continue;
+    const long wgs = (long)nb * tiles * ((g.L3 + ch - 1) / ch);
+    cand.push_back({((wgs + cus - 1) / cus) * (ch + 4), ch});
+  }
+  std::stable_sort(cand.begin(), cand.end(),
+                   [](const std::pair<long, int>& a, const std::pair<long, int>& b) {
+                     return a.first < b.first;
+                   });
+  *out = cand[0].second;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return ST_OK;
+  const int ncand = (int)std::min<size_t>(4, cand.size());
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ncand > 1 && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    float best_ms = -1.0f;
+    bool ok = true;
+    for (int r = 0; r < 2 && ok; ++r)  // the first round also warms the caches
+      for (int k = 0; k < ncand && ok; ++k) {
+        ok = hipEventRecord(e0, c->stream) == hipSuccess;
+        if (ok) PBR_TRY(launch(cand[k].second));
+        ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (ok && r == 1 && (best_ms < 0.0f || ms < best_ms)) {
+          best_ms = ms;
+          *out = cand[k].second;
+        }
+      }
+    if (!ok) *out = cand[0].second;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  auto& slot = c->stencil_tune[c->stencil_tune_next];
+  c->stencil_tune_next = (c->stencil_tune_next + 1) % PBR_TUNE_SLOTS;
+  slot.nb = nb;
+  slot.L1 = g.L1;
+  slot.L2 = g.L2;
+  slot.L3 = g.L3;
+  slot.chunk = *out;
+  return ST_OK;
+}
+
+bool apply_tuned(const pbr_ctx* c, const Geo& g, int nb) {
+  for (const auto& e : c->stencil_tune)
+    if (e.nb == nb && e.L1 == g.L1 && e.L2 == g.L2 && e.L3 == g.L3 && e.chunk > 0) return true;
+  return false;
+}
+
 long apply_partials(const pbr_ctx* c, int block) {
   const long L1 = c->n1, L2 = block < 0 ? c->n2 : c->n2 / 2, L3 = block < 0 ? c->n3 : c->n3 / 2;
   return ((L1 + TILE_I - 1) / TILE_I) * ((L2 + TILE_J - 1) / TILE_J) *
@@ -540,28 +614,7 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
   A.s = s;
   A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
   A.tiles_j = (g.L2 + TILE_J - 1) / TILE_J;
-  // chunk length: one work-group fits a CU at a time (LDS and registers), so
-  // a launch runs in ceil(work-groups / CUs) rounds, each as long as its
-  // longest chunk plus its start-up (the two partial planes a chunk computes at
-  // its ends and the first loads, which nothing overlaps): pick the chunk that
-  // minimises rounds x (chunk + 4) for this batch among whole groups of
-  // PART_G planes (or the whole box), so no result depends on the choice.
   const long tiles = (long)A.tiles_i * A.tiles_j;
-  const int cus = std::max(1, c->cus);
-  int chunk = g.L3;
-  long best = -1;
-  for (int ch = std::min(PART_G, g.L3); ch <= g.L3; ++ch) {
-    if (ch % PART_G != 0 && ch != g.L3) continue;
-    const long wgs = (long)nb * tiles * ((g.L3 + ch - 1) / ch);
-    const long cost = ((wgs + cus - 1) / cus) * (ch + 4);
-    if (best < 0 || cost < best) {
-      best = cost;
-      chunk = ch;
-    }
-  }
-  A.chunk = chunk;
-  const int nchunks = (g.L3 + chunk - 1) / chunk;
-  A.per = (int)(tiles * nchunks);
   const long np = tiles * ((g.L3 + PART_G - 1) / PART_G);  // (x, y) partials per layout
   if (nparts) *nparts = (int)np;
   for (int t = 0; t < nb; ++t) {
@@ -580,11 +633,18 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
       return ST_EINVAL;
     }
   }
-  const unsigned grid = (unsigned)((long)A.per * nb);
-  hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
-                     dim3(tile_threads(TILE_I, TILE_J)), 0, c->stream, A);
-  PBR_HIP(c, hipGetLastError());
-  return ST_OK;
+  auto launch = [&](int chunk) -> int {
+    A.chunk = chunk;
+    A.per = (int)(tiles * ((g.L3 + chunk - 1) / chunk));
+    const unsigned grid = (unsigned)((long)A.per * nb);
+    hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
+                       dim3(tile_threads(TILE_I, TILE_J)), 0, c->stream, A);
+    PBR_HIP(c, hipGetLastError());
+    return ST_OK;
+  };
+  int chunk = 0;
+  PBR_TRY(tuned_chunk(c, g, nb, tiles, launch, &chunk));
+  return launch(chunk);
 }
 
 int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,

@@ -74,6 +74,25 @@ def test_apply_blocks_batched(dims):
     ctx.close()
 
 
+def test_autotuned_split_does_not_change_results():
+    """The first four-block launch of a box is autotuned (several work splits
+    timed with the caller's own launches); its output must equal every later
+    launch's and a fresh context's, bit for bit (n=64: several candidate chunks)."""
+    dims = (64, 64, 64)
+    C21, rho = random_spd_field(dims, seed=3)
+    n = int(np.prod(dims))
+    x = to_dev(complex_gaussian(3 * n, seed=77))
+    kap, s = (0.2, 0.1, -0.3), 0.6
+    outs = []
+    for rep in range(2):
+        ctx = make_ctx(dims, C21, rho)
+        for call in range(2):
+            outs.append(to_host(ctx.apply_blocks(kap, s, x, to_dev(np.zeros(3 * n, complex)))))
+        ctx.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_apply_blocks_rejects_odd_grid():
     C21, rho = random_spd_field((3, 4, 4), seed=1)
     ctx = make_ctx((3, 4, 4), C21, rho)
