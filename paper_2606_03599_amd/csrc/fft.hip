@@ -109,7 +109,9 @@ constexpr int plan_fac(int L, int s) {
 }
 
 // One Stockham stage on nb lines of length L stored back to back in LDS.
-template <int L, int R, int NS, int SIGN>
+// Lines sit in LDS P >= L elements apart (P = L + 1 keeps a transposing access,
+// one lane per line, off a single bank group).
+template <int L, int P, int R, int NS, int SIGN>
 __device__ inline void stage(const cplx* __restrict__ roots, const cplx* src, cplx* dst, int nb) {
   constexpr int LR = L / R;
   constexpr int TW = L / (NS * R);
@@ -120,28 +122,28 @@ __device__ inline void stage(const cplx* __restrict__ roots, const cplx* src, cp
     cplx v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      cplx x = src[b * L + j + r * LR];
+      cplx x = src[b * P + j + r * LR];
       if (r > 0 && NS > 1) x = cmul(x, cj(roots[(jm * r * TW) % L], SIGN > 0));
       v[r] = x;
     }
     small_dft<R, SIGN>(v);
     const int idx = (j / NS) * NS * R + jm;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[b * L + idx + r * NS] = v[r];
+    for (int r = 0; r < R; ++r) dst[b * P + idx + r * NS] = v[r];
   }
 }
 
 // Stages S.. of a length-L transform of nb lines; the input is in a, the
 // other buffer is b; returns the buffer that holds the result.
-template <int L, int S, int NS, int SIGN>
+template <int L, int P, int S, int NS, int SIGN>
 __device__ inline cplx* fft_stages(const cplx* __restrict__ roots, cplx* a, cplx* b, int nb) {
   if constexpr (S >= plan_nfac(L)) {
     return a;
   } else {
     constexpr int R = plan_fac(L, S);
-    stage<L, R, NS, SIGN>(roots, a, b, nb);
+    stage<L, P, R, NS, SIGN>(roots, a, b, nb);
     __syncthreads();
-    return fft_stages<L, S + 1, NS * R, SIGN>(roots, b, a, nb);
+    return fft_stages<L, P, S + 1, NS * R, SIGN>(roots, b, a, nb);
   }
 }
 
@@ -193,14 +195,64 @@ template <int LT, int AXIS, int SPLIT, int SIGN, int MODE>
 __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   constexpr int LM = SPLIT ? 2 * LT : LT;          // line length in memory
   constexpr int B = (FFT_ELEMS / LM) > 0 ? FFT_ELEMS / LM : 1;  // lines per work-group
-  __shared__ cplx buf0[B * LM], buf1[B * LM];
+  constexpr int PL = LT + 1;                      // LDS pitch of a line
+  __shared__ cplx buf0[(SPLIT ? 2 * B : B) * PL], buf1[(SPLIT ? 2 * B : B) * PL];
+  __shared__ cplx roots_s[LT], twist_s[LT];  // the stages' twiddles and this layout's twist
   __shared__ double red[FFT_THREADS / 64 + 1];
   const PcgHook& H = A.b[blockIdx.z].h;
   const cplx* in_ = A.b[blockIdx.z].in;
   cplx* out_ = A.b[blockIdx.z].out;
-  const cplx* __restrict__ twist = A.b[blockIdx.z].twist;
+  const cplx* __restrict__ twist = twist_s;
   PcgScalars* st = H.st;
   const bool first_wg = blockIdx.x == 0 && blockIdx.y == 0;
+  const int comp = blockIdx.y;
+  const long l0 = (long)blockIdx.x * B;
+  const int nb = (int)min((long)B, A.nlines - l0);
+  const long co = comp * A.N;
+  const long es = AXIS == 0 ? 1 : A.L1;
+  auto base_of = [&](long l) -> long {
+    if (AXIS == 0) return l * LM;
+    return (l % A.L1) + (l / A.L1) * (long)A.L1 * A.L2;
+  };
+  // element p of this thread: w = threadIdx.x + p * FFT_THREADS
+  constexpr int PER = (B * LM + FFT_THREADS - 1) / FFT_THREADS;
+  auto elem = [&](int w, int& b, int& e) {
+    if (AXIS == 0) {
+      b = w / LM;
+      e = w - b * LM;
+    } else {
+      e = w / B;
+      b = w - e * B;
+    }
+  };
+  // Operands are loaded first, before the CG scalars (which need the partials
+  // of the previous launch) and the convergence flag, so their latency overlaps
+  // those reads: MODE 1 x, p, r, q (or b at init); MODE 2 the old p; else the input.
+  cplx va[PER], vb[PER], vc[PER], vd[PER];
+  long ix[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int w = threadIdx.x + p * FFT_THREADS;
+    int b, e;
+    elem(w, b, e);
+    const bool ok = w < B * LM && b < nb;
+    ix[p] = ok ? co + base_of(l0 + b) + e * es : -1;
+    va[p] = vb[p] = vc[p] = vd[p] = mk(0, 0);
+    if (!ok) continue;
+    if (MODE == 1) {
+      if (H.init) {
+        va[p] = H.b[ix[p]];
+      } else {
+        va[p] = H.x[ix[p]];
+        vb[p] = H.p[ix[p]];
+        vc[p] = H.r[ix[p]];
+        vd[p] = H.q[ix[p]];
+      }
+    } else {
+      va[p] = in_[ix[p]];
+      if (MODE == 2 && !H.init) vb[p] = out_[ix[p]];
+    }
+  }
   if (st && !(MODE == 1 && H.init) && st->done) return;  // uniform per work-group
   double alpha = 0.0;
   if (MODE == 1) {
@@ -234,74 +286,61 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
     beta = st->beta;
     if (first_wg && threadIdx.x == 0) st->rz = st->rz_next;
   }
-  const int comp = blockIdx.y;
-  const long l0 = (long)blockIdx.x * B;
-  const int nb = (int)min((long)B, A.nlines - l0);
-  const long co = comp * A.N;
-  const long es = AXIS == 0 ? 1 : A.L1;
-  auto base_of = [&](long l) -> long {
-    if (AXIS == 0) return l * LM;
-    return (l % A.L1) + (l / A.L1) * (long)A.L1 * A.L2;
-  };
+  // (visible to the stages and the output loop after the barrier that follows
+  // the input loop; the input loop itself reads the twist from global memory)
+  for (int t = threadIdx.x; t < LT; t += blockDim.x) {
+    roots_s[t] = A.roots[t];
+    twist_s[t] = A.b[blockIdx.z].twist[t];
+  }
+  const cplx* __restrict__ twist_g = A.b[blockIdx.z].twist;
   double rr = 0.0;
-  for (int w = threadIdx.x; w < B * LM; w += blockDim.x) {
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    if (ix[p] < 0) continue;
+    const int w = threadIdx.x + p * FFT_THREADS;
     int b, e;
-    if (AXIS == 0) {
-      b = w / LM;
-      e = w - b * LM;
-    } else {
-      e = w / B;
-      b = w - e * B;
-    }
-    if (b < nb) {
-      const long idx = co + base_of(l0 + b) + e * es;
-      cplx x;
-      if (MODE == 1) {
-        if (H.init) {
-          x = H.b[idx];
-          H.r[idx] = x;
-          H.x[idx] = mk(0, 0);
-        } else {
-          H.x[idx] = cfma(alpha, H.p[idx], H.x[idx]);
-          x = cfma(-alpha, H.q[idx], H.r[idx]);
-          H.r[idx] = x;
-        }
-        rr = fma(x.x, x.x, fma(x.y, x.y, rr));
+    elem(w, b, e);
+    const long idx = ix[p];
+    cplx x;
+    if (MODE == 1) {
+      if (H.init) {
+        x = va[p];
+        H.r[idx] = x;
+        H.x[idx] = mk(0, 0);
       } else {
-        x = in_[idx];
+        H.x[idx] = cfma(alpha, vb[p], va[p]);
+        x = cfma(-alpha, vd[p], vc[p]);
+        H.r[idx] = x;
       }
-      const int slot = SPLIT ? 2 * b + (e & 1) : b;
-      const int y = SPLIT ? e >> 1 : e;
-      if (SIGN < 0) x = cmul(x, twist[y]);
-      buf0[slot * LT + y] = x;
+      rr = fma(x.x, x.x, fma(x.y, x.y, rr));
+    } else {
+      x = va[p];
     }
+    const int slot = SPLIT ? 2 * b + (e & 1) : b;
+    const int y = SPLIT ? e >> 1 : e;
+    if (SIGN < 0) x = cmul(x, twist_g[y]);
+    buf0[slot * PL + y] = x;
   }
   if (MODE == 1) {
     const double s = block_sum_all(rr, red);
     if (threadIdx.x == 0) H.part_out[comp * gridDim.x + blockIdx.x] = s;
   }
   __syncthreads();
-  const cplx* res = fft_stages<LT, 0, 1, SIGN>(A.roots, buf0, buf1, SPLIT ? 2 * nb : nb);
-  for (int w = threadIdx.x; w < B * LM; w += blockDim.x) {
+  const cplx* res = fft_stages<LT, PL, 0, 1, SIGN>(roots_s, buf0, buf1, SPLIT ? 2 * nb : nb);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    if (ix[p] < 0) continue;
+    const int w = threadIdx.x + p * FFT_THREADS;
     int b, e;
-    if (AXIS == 0) {
-      b = w / LM;
-      e = w - b * LM;
-    } else {
-      e = w / B;
-      b = w - e * B;
-    }
-    if (b < nb) {
-      const int slot = SPLIT ? 2 * b + (e & 1) : b;
-      const int y = SPLIT ? e >> 1 : e;
-      cplx x = res[slot * LT + y];
-      if (SIGN > 0) x = cmul(x, cconj(twist[y]));
-      const long idx = co + base_of(l0 + b) + e * es;
-      if (MODE == 2 && !H.init)
-        out_[idx] = cfma(beta, out_[idx], cscale(A.scale, x));
-      else
-        out_[idx] = cscale(A.scale, x);
-    }
+    elem(w, b, e);
+    const int slot = SPLIT ? 2 * b + (e & 1) : b;
+    const int y = SPLIT ? e >> 1 : e;
+    cplx x = res[slot * PL + y];
+    if (SIGN > 0) x = cmul(x, cconj(twist[y]));
+    if (MODE == 2 && !H.init)
+      out_[ix[p]] = cfma(beta, vb[p], cscale(A.scale, x));
+    else
+      out_[ix[p]] = cscale(A.scale, x);
   }
 }
 
@@ -408,33 +447,50 @@ template <int L3T, int BLK>
 __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   constexpr int BI = solve_bi(L3T, BLK);
   constexpr int NL = 3 * BI;  // lines of one work-group: component-major
-  __shared__ cplx buf0[NL * L3T], buf1[NL * L3T];
+  constexpr int PT = L3T + 1;  // LDS pitch of a line
+  __shared__ cplx buf0[NL * PT], buf1[NL * PT];
+  __shared__ cplx roots_s[L3T], twist_s[L3T], e3_s[L3T], e1_s[BI];
   __shared__ double red[FFT_THREADS / 64 + 1];
   cplx* const data = S.b[blockIdx.y].data;
   PcgScalars* const st = S.b[blockIdx.y].st;
   double* const part_out = S.b[blockIdx.y].part_out;
   const int ca = S.b[blockIdx.y].a, cc = S.b[blockIdx.y].c;
-  const cplx* __restrict__ twist = S.b[blockIdx.y].twist;
-  const cplx* __restrict__ e1 = S.b[blockIdx.y].e1;
   const cplx* __restrict__ e2 = S.b[blockIdx.y].e2;
-  const cplx* __restrict__ e3 = S.b[blockIdx.y].e3;
-  if (st && st->done) return;
   const int groups_i = (S.L1 + BI - 1) / BI;
   const int q = blockIdx.x / groups_i;
   const int i0 = (blockIdx.x % groups_i) * BI;
   const int bi = min(BI, S.L1 - i0);
   const long kstride = (long)S.L1 * S.L2;
   const long base = i0 + (long)S.L1 * q;
+  // tables of this work-group in LDS: twiddles, twist, e^{i gamma_r}, and
+  // e^{i alpha} of its i-values (block: of its BI/2 sub-lattice pairs)
+  {
+    const cplx* __restrict__ e1g = S.b[blockIdx.y].e1;
+    const int e1o = BLK ? (i0 >> 1) : i0;
+    for (int t = threadIdx.x; t < L3T; t += blockDim.x) {
+      roots_s[t] = S.roots[t];
+      twist_s[t] = S.b[blockIdx.y].twist[t];
+      e3_s[t] = S.b[blockIdx.y].e3[t];
+    }
+    for (int t = threadIdx.x; t < (BLK ? bi / 2 : bi); t += blockDim.x) e1_s[t] = e1g[e1o + t];
+  }
+  // (the tables are read after the barrier below; the input loop reads the
+  // twist from global memory)
+  const cplx* __restrict__ twist = twist_s;
+  const cplx* __restrict__ e3 = e3_s;
+  const cplx* __restrict__ twist_g = S.b[blockIdx.y].twist;
   for (int w = threadIdx.x; w < NL * L3T; w += blockDim.x) {
     const int y = w / NL;
     const int rem = w - y * NL;
     const int comp = rem / BI, di = rem - comp * BI;
     if (di < bi)
-      buf0[(comp * BI + di) * L3T + y] =
-          cmul(data[comp * S.N + base + di + y * kstride], twist[y]);
+      buf0[(comp * BI + di) * PT + y] =
+          cmul(data[comp * S.N + base + di + y * kstride], twist_g[y]);
   }
+  // (the operands are requested before the convergence flag is read)
+  if (st && st->done) return;  // uniform per work-group
   __syncthreads();
-  cplx* f = fft_stages<L3T, 0, 1, -1>(S.roots, buf0, buf1, NL);
+  cplx* f = fft_stages<L3T, PT, 0, 1, -1>(roots_s, buf0, buf1, NL);
   cplx* g = (f == buf0) ? buf1 : buf0;
   const cplx Eb = e2[q];
   double rz = 0.0;  // sum over this work-group's modes of Re(c^H K^-1 c)
@@ -443,11 +499,11 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       const int di = w / L3T, r = w - di * L3T;
       cplx bv[3], xv[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) bv[a] = f[(a * BI + di) * L3T + r];
-      mode_solve(S, e1[i0 + di], Eb, e3[r], bv, xv);
+      for (int a = 0; a < 3; ++a) bv[a] = f[(a * BI + di) * PT + r];
+      mode_solve(S, e1_s[di], Eb, e3[r], bv, xv);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        g[(a * BI + di) * L3T + r] = xv[a];
+        g[(a * BI + di) * PT + r] = xv[a];
         rz = fma(bv[a].x, xv[a].x, fma(bv[a].y, xv[a].y, rz));
       }
     }
@@ -457,7 +513,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     for (int w = threadIdx.x; w < (bi / 2) * L3T; w += blockDim.x) {
       const int dp = w / L3T, r = w - dp * L3T;
       const int m1p = (i0 >> 1) + dp;
-      const cplx Ea = e1[m1p], Eg = e3[r];
+      const cplx Ea = e1_s[dp], Eg = e3[r];
       // T_p = e^{-i(o2 beta + o3 gamma)}: conj(Eb)^o2 conj(Eg)^o3
       const cplx cb = cconj(Eb), cg = cconj(Eg);
       const cplx one = mk(1.0, 0.0);
@@ -467,8 +523,8 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       cplx c0[3], c1[3], z0[3], z1[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const cplx v0 = cmul(T0, f[(a * BI + 2 * dp) * L3T + r]);
-        const cplx v1 = cmul(t1e, f[(a * BI + 2 * dp + 1) * L3T + r]);
+        const cplx v0 = cmul(T0, f[(a * BI + 2 * dp) * PT + r]);
+        const cplx v1 = cmul(t1e, f[(a * BI + 2 * dp + 1) * PT + r]);
         c0[a] = cadd(v0, v1);
         c1[a] = csub(v0, v1);
       }
@@ -478,8 +534,8 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       for (int a = 0; a < 3; ++a) {
         rz = fma(c0[a].x, z0[a].x, fma(c0[a].y, z0[a].y, rz));
         rz = fma(c1[a].x, z1[a].x, fma(c1[a].y, z1[a].y, rz));
-        g[(a * BI + 2 * dp) * L3T + r] = cmulc(T0, cadd(z0[a], z1[a]));
-        g[(a * BI + 2 * dp + 1) * L3T + r] = cmulc(t1e, csub(z0[a], z1[a]));
+        g[(a * BI + 2 * dp) * PT + r] = cmulc(T0, cadd(z0[a], z1[a]));
+        g[(a * BI + 2 * dp + 1) * PT + r] = cmulc(t1e, csub(z0[a], z1[a]));
       }
     }
   }
@@ -488,14 +544,14 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     if (threadIdx.x == 0) part_out[blockIdx.x] = v;
   }
   __syncthreads();
-  const cplx* res = fft_stages<L3T, 0, 1, +1>(S.roots, g, f, NL);
+  const cplx* res = fft_stages<L3T, PT, 0, 1, +1>(roots_s, g, f, NL);
   for (int w = threadIdx.x; w < NL * L3T; w += blockDim.x) {
     const int y = w / NL;
     const int rem = w - y * NL;
     const int comp = rem / BI, di = rem - comp * BI;
     if (di < bi)
       data[comp * S.N + base + di + y * kstride] =
-          cmul(res[(comp * BI + di) * L3T + y], cconj(twist[y]));
+          cmul(res[(comp * BI + di) * PT + y], cconj(twist[y]));
   }
 }
 
