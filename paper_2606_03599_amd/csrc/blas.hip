@@ -430,6 +430,39 @@ int pcg_xr(pbr_ctx* c, hipStream_t st_, long n, cplx* x, cplx* r, const cplx* p,
   return ST_OK;
 }
 
+// The x update a fused PCG iteration defers to its last pass, for the layouts
+// whose last iteration was cut short by convergence (done == 1): x += alpha p.
+struct FixX {
+  long n;
+  const PcgScalars* st[PBR_MAX_BATCH];
+  cplx* x[PBR_MAX_BATCH];
+  const cplx* p[PBR_MAX_BATCH];
+};
+__global__ void pcg_fix_x_kernel(FixX F) {
+  const PcgScalars* st = F.st[blockIdx.y];
+  if (st->done != 1) return;
+  const double a = st->alpha;
+  cplx* x = F.x[blockIdx.y];
+  const cplx* p = F.p[blockIdx.y];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < F.n;
+       i += (long)gridDim.x * blockDim.x)
+    x[i] = cfma(a, p[i], x[i]);
+}
+
+int pcg_fix_x(pbr_ctx* c, hipStream_t st_, long n, int nb, PcgScalars* const* st,
+              cplx* const* x, const cplx* const* p) {
+  FixX F;
+  F.n = n;
+  for (int t = 0; t < nb; ++t) {
+    F.st[t] = st[t];
+    F.x[t] = x[t];
+    F.p[t] = p[t];
+  }
+  hipLaunchKernelGGL(pcg_fix_x_kernel, dim3(grid_for(n), nb), dim3(RT), 0, st_, F);
+  PBR_HIP(c, hipGetLastError());
+  return ST_OK;
+}
+
 int pcg_beta_p(pbr_ctx* c, hipStream_t st_, long n, const cplx* r, const cplx* z, cplx* p, double* part,
                PcgScalars* st) {
   const unsigned g = grid_for(n);

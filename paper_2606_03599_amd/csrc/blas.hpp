@@ -62,5 +62,9 @@ int pcg_init_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* r, const cpl
 int pcg_alpha(pbr_ctx* c, hipStream_t st_, long n, const cplx* p, const cplx* q, double* part, PcgScalars* st);
 int pcg_xr(pbr_ctx* c, hipStream_t st_, long n, cplx* x, cplx* r, const cplx* p, const cplx* q, double* part,
            PcgScalars* st);
+// x += alpha p for the layouts of a fused PCG batch whose last iteration ended
+// at the convergence test (the deferred update of the last pass)
+int pcg_fix_x(pbr_ctx* c, hipStream_t st_, long n, int nb, PcgScalars* const* st,
+              cplx* const* x, const cplx* const* p);
 int pcg_beta_p(pbr_ctx* c, hipStream_t st_, long n, const cplx* r, const cplx* z, cplx* p, double* part,
                PcgScalars* st);

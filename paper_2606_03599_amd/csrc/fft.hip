@@ -189,8 +189,10 @@ __device__ inline void pcg_finish(const PcgHook& H, double* sh) {
 // LT: transform length; AXIS: 0 (memory-contiguous lines of length LM) or 1;
 // SPLIT: axis-0 lines of a block, LM = 2 LT, even and odd elements transformed
 // separately.  MODE: 0 plain; 1 first PCG pass (input r after the update
-// r -= alpha q, x += alpha p, or r = b, x = 0 at init; |r|^2 partials);
-// 2 last PCG pass (output p = scale z + beta p instead of z).
+// r -= alpha q, or r = b, x = 0 at init; |r|^2 partials); 2 last PCG pass
+// (output p = scale z + beta p instead of z, and the update x += alpha p with
+// the old p, deferred from the first pass so that pass reads neither x nor p;
+// an iteration cut short by convergence gets it from pcg_fix_x).
 template <int LT, int AXIS, int SPLIT, int SIGN, int MODE>
 __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   constexpr int LM = SPLIT ? 2 * LT : LT;          // line length in memory
@@ -227,7 +229,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   };
   // Operands are loaded first, before the CG scalars (which need the partials
   // of the previous launch) and the convergence flag, so their latency overlaps
-  // those reads: MODE 1 x, p, r, q (or b at init); MODE 2 the old p; else the input.
+  // those reads: MODE 1 r, q (or b at init); MODE 2 the old p and x; else the input.
   cplx va[PER], vb[PER], vc[PER], vd[PER];
   long ix[PER];
 #pragma unroll
@@ -243,14 +245,15 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
       if (H.init) {
         va[p] = H.b[ix[p]];
       } else {
-        va[p] = H.x[ix[p]];
-        vb[p] = H.p[ix[p]];
         vc[p] = H.r[ix[p]];
         vd[p] = H.q[ix[p]];
       }
     } else {
       va[p] = in_[ix[p]];
-      if (MODE == 2 && !H.init) vb[p] = out_[ix[p]];
+      if (MODE == 2 && !H.init) {
+        vb[p] = out_[ix[p]];
+        vc[p] = H.x[ix[p]];
+      }
     }
   }
   if (st && !(MODE == 1 && H.init) && st->done) return;  // uniform per work-group
@@ -281,9 +284,10 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   } else if (st && H.role && first_wg) {
     pcg_finish(H, red);
   }
-  double beta = 0.0;
+  double beta = 0.0, alpha_x = 0.0;
   if (MODE == 2) {
     beta = st->beta;
+    alpha_x = st->alpha;
     if (first_wg && threadIdx.x == 0) st->rz = st->rz_next;
   }
   // (visible to the stages and the output loop after the barrier that follows
@@ -308,7 +312,6 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
         H.r[idx] = x;
         H.x[idx] = mk(0, 0);
       } else {
-        H.x[idx] = cfma(alpha, vb[p], va[p]);
         x = cfma(-alpha, vd[p], vc[p]);
         H.r[idx] = x;
       }
@@ -337,10 +340,12 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
     const int y = SPLIT ? e >> 1 : e;
     cplx x = res[slot * PL + y];
     if (SIGN > 0) x = cmul(x, cconj(twist[y]));
-    if (MODE == 2 && !H.init)
+    if (MODE == 2 && !H.init) {
       out_[ix[p]] = cfma(beta, vb[p], cscale(A.scale, x));
-    else
+      H.x[ix[p]] = cfma(alpha_x, vb[p], vc[p]);
+    } else {
       out_[ix[p]] = cscale(A.scale, x);
+    }
   }
 }
 
@@ -806,7 +811,8 @@ int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift)
     io4[t] = LineIO{P[t].z, P[t].z, T.twist[1], h};
     io4[t].h.role = 2;  // first work-group finishes (r, z) and beta
     io4[t].h.red_in = P[t].part_rz;
-    io5[t] = LineIO{P[t].z, P[t].pout, T.twist[0], h};  // p = z + beta p
+    io5[t] = LineIO{P[t].z, P[t].pout, T.twist[0], h};  // p = z + beta p, x += alpha p
+    io5[t].h.x = P[t].x;
     sio[t] = SolveIO{P[t].block, P[t].z, P[t].st, P[t].part_rz, &T};
   }
   PBR_TRY(run_lines(c, T0, blocked, nb, 0, -1, 1, io1, 1.0, cap, &n_rr));

@@ -338,7 +338,8 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const LayoutRef* L, double shift,
       PBR_TRY(pcg_plain(c, L[t].slot, L[t].block, L[t].kappa, shift, b[t], x[t], o));
   } else {
     // fused iteration: matvec (+ (p, q) partials) and five preconditioner passes
-    // that also update x, r and p and finish the CG scalars on the device
+    // that also update r, p and x (x in the last pass, with the old p) and
+    // finish the CG scalars on the device
     const Geo g = make_geo(c, L[0].block, L[0].kappa);
     PcgStep P[PBR_MAX_BATCH];
     ApplyLayout AL[PBR_MAX_BATCH];
@@ -407,6 +408,14 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const LayoutRef* L, double shift,
       }
       if (all) break;
     }
+    // the x update of an iteration that ended at the convergence test
+    PcgScalars* sts[PBR_MAX_BATCH];
+    const cplx* ps[PBR_MAX_BATCH];
+    for (int t = 0; t < nb; ++t) {
+      sts[t] = P[t].st;
+      ps[t] = P[t].p;
+    }
+    PBR_TRY(pcg_fix_x(c, c->stream, 3 * c->layout_nodes(L[0].block), nb, sts, x, ps));
   }
   PBR_TRY(read_states(c, hs));
   int status = ST_OK;
