@@ -366,23 +366,31 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
 
   // ---- prologue: velocity planes k0-2 .. k0 staged, k0+1 in registers;
   //      stiffness of tau planes k0-1 and k0 in flight ----
+  //      (all of them requested together, so the start-up waits for one
+  //      round trip to memory rather than one per plane)
   cplx XA[XPASS][3], XB[XPASS][3];
-  for (int v = k0 - 2; v <= k0; ++v) {
-    stage_load(v, true, XA);
-    stage_store(v, XA);
+  bool need_a = needed_at(k0 - 1), need_b = needed_at(k0);
+  double Ca[22], Cb[22];
+  {
+    cplx X0[XPASS][3], X1[XPASS][3];
+    stage_load(k0 - 2, true, X0);
+    stage_load(k0 - 1, true, X1);
+    stage_load(k0, true, XA);
+    stage_load(k0 + 1, k0 + 1 <= k1 + 1, XB);
+    __builtin_amdgcn_sched_barrier(0);
+    load_C(k0 - 1, need_a, Ca);
+    // keep the two sets in issue order: the loop's waits count on it
+    __builtin_amdgcn_sched_barrier(0);
+    load_C(k0, need_b, Cb);
+    stage_store(k0 - 2, X0);
+    stage_store(k0 - 1, X1);
+    stage_store(k0, XA);
   }
-  stage_load(k0 + 1, k0 + 1 <= k1 + 1, XB);
   // Prefetch distances: the stiffness of plane s+2 is loaded right after the
   // stress of plane s has consumed its registers (two sets alternate), and the
   // velocity of plane s+3 is loaded at the top of step s and staged at the end
   // of step s+1 (two register sets alternate), so every load has more than a
   // whole step to arrive and no step waits for loads it issued itself.
-  bool need_a = needed_at(k0 - 1), need_b = needed_at(k0);
-  double Ca[22], Cb[22];
-  load_C(k0 - 1, need_a, Ca);
-  // keep the two sets in issue order: the loop's waits count on it
-  __builtin_amdgcn_sched_barrier(0);
-  load_C(k0, need_b, Cb);
   const double shift = A.s;
   __syncthreads();
 
