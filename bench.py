@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=0)
-    p.add_argument("--study", choices=("refinement", "cells"), default=None,
+    p.add_argument("--study", choices=("refinement", "cells", "gap"), default=None,
                    help="refinement: grid-refinement errors of the FCC workload at X, W and L "
                         "against a 256^3 blocked reference (one JSON line)")
     p.add_argument("--workload", choices=("cube", "fcc"), default="cube",
@@ -214,6 +214,70 @@ def refinement_study(grids=(16, 32, 64, 128), ref=256, nev=8, points=("X", "W", 
             "observed_order": order, "seconds": round(time.perf_counter() - t0, 1)}
 
 
+def gap_gradient_study(n, nev, points=("X", "R"), seed=0):
+    """Large-grid slice of the batching + differentiation workload: the two-phase
+    cell at n^3, the blocked band path at X and R with nev eigenpairs (four
+    blocks in lockstep), then the gradient of the gap width lambda_7 - lambda_6
+    at X with respect to the nodewise C21 and rho (Hellmann-Feynman, strains
+    recomputed on the device), checked along one random direction over 50 nodes
+    against a central difference with relative step 1e-6."""
+    import numpy as np
+    import torch
+    from paper_2606_03599_amd import pbr
+    from paper_2606_03599_amd.autograd import band_eigenvalues
+    from synth import SC_POINTS, two_phase_cell
+    dims = (n, n, n)
+    C21, rho = two_phase_cell(dims, radius=0.35, seed=seed)[:2]
+    ctx = pbr.Context(dims)
+    Ct = torch.tensor(C21, device="cuda", requires_grad=True)
+    rt = torch.tensor(rho, device="cuda", requires_grad=True)
+    ctx.set_material(Ct.detach(), rt.detach())
+    kps = [SC_POINTS[p] for p in points]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, st = ctx.band_path(kps, nev)
+    t_path = time.perf_counter() - t0
+    log(f"n={n} blocked path at {points}, nev={nev}: {t_path:.1f} s, {st.op_applies} solves, "
+        f"{st.pcg_avg:.1f} PCG iterations per solve")
+    kap = SC_POINTS[points[0]]
+    t0 = time.perf_counter()
+    lam = band_eigenvalues(ctx, kap, Ct, rt, 8)
+    gap = lam[6] - lam[5]
+    gC, gr = torch.autograd.grad(gap, [Ct, rt])
+    gap = float(gap.detach())
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    log(f"gap lambda_7 - lambda_6 at {points[0]} = {gap:.6e}, eigenvalues and gradient "
+        f"{t_grad:.1f} s")
+    rng = np.random.default_rng(256)
+    nodes = rng.choice(C21.shape[0], size=50, replace=False)
+    dC = np.zeros((50, 21)) + rng.standard_normal((50, 21)) * np.abs(C21[nodes]).mean()
+    dr = rng.standard_normal(50) * rho[nodes]
+    ana = float((gC[nodes].cpu().numpy() * dC).sum() + (gr[nodes].cpu().numpy() * dr).sum())
+    h = 1e-6
+    fd = 0.0
+    for sgn in (1.0, -1.0):
+        C2, r2 = C21.copy(), rho.copy()
+        C2[nodes] += sgn * h * dC
+        r2[nodes] += sgn * h * dr
+        l2 = band_eigenvalues(ctx, kap, torch.tensor(C2, device="cuda"),
+                              torch.tensor(r2, device="cuda"), 8).cpu().numpy()
+        fd += sgn * (l2[6] - l2[5]) / (2 * h)
+        del C2, r2
+    log(f"directional derivative of the gap: analytic {ana:.6e}, central difference {fd:.6e}")
+    ctx.close()
+    return {"study": "large grid: blocked band path and the gradient of a gap width",
+            "workload": f"two-phase unit cube n={n}^3 ({n ** 3} nodes, {n ** 3 // 4} per block), "
+                        f"blocked path at {list(points)}, {nev} lowest eigenpairs per k; gap "
+                        f"lambda_7 - lambda_6 at {points[0]}",
+            "path_s": round(t_path, 3), "solves": st.op_applies, "pcg_avg": round(st.pcg_avg, 2),
+            "eigenvalues": {p: [float(x) for x in e[:8]] for p, e in zip(points, ev)},
+            "gap": gap, "eigs_and_gradient_s": round(t_grad, 3),
+            "grad_norms": {"C21": float(gC.norm()), "rho": float(gr.norm())},
+            "directional_check": {"analytic": ana, "central_difference": fd,
+                                  "rel_diff": abs(ana - fd) / max(abs(fd), 1e-300)}}
+
+
 def cells_study(nk, nev, count=8, seed=0):
     """Uneven batch of two-phase cells (n drawn from {64, 96, 128}, inclusion
     radius from U[0.2, 0.4], each with its own seeded inclusion stiffness): the
@@ -267,6 +331,10 @@ def main():
         sys.exit(2)
     if args.study == "refinement":
         print(json.dumps(refinement_study()), flush=True)
+        return
+    if args.study == "gap":
+        print(json.dumps(gap_gradient_study(args.n if args.n > 0 else 256,
+                                            args.nev if args.nev > 0 else 30)), flush=True)
         return
     if args.study == "cells":
         print(json.dumps(cells_study(args.nk if args.nk != 16 else 6,
