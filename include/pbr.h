@@ -88,6 +88,12 @@ typedef struct pbr_opts {
   int graphs;        /* 1 = each chunk of check_every PCG iterations is captured once
                         as a HIP graph (per k, shift and set of layouts) and replayed;
                         0 = kernels launched one by one.  Results are identical. */
+  int warm_start;    /* pbr_eigs_merged / pbr_band_path: 1 = the Krylov start vector of a
+                        solve is the sum of the Ritz vectors of the same layout at the
+                        last wave vector of the previous group of 4 (or of its own
+                        previous run when a block is re-solved with more eigenpairs),
+                        plus a random part of half that norm; 0 = random start.  The
+                        eigenvalues agree to the tolerance; fewer restarts along a path. */
 } pbr_opts;
 
 /* Statistics of one pbr_solve / pbr_eigs / pbr_eigs_merged / pbr_band_path call. */
@@ -107,7 +113,7 @@ typedef struct pbr_stats {
 
 /* Fill *o with the defaults: tol 1e-12, tol_inner 1e-12, maxit 300 / 200,
  * ncv automatic, precond 1, check_every automatic, seed 1, concurrent 1,
- * graphs 1. */
+ * graphs 1, warm_start 1. */
 void pbr_opts_default(pbr_opts *o);
 
 /* Create a context for an n1 x n2 x n3 grid on HIP device `hip_device`.

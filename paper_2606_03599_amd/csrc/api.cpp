@@ -60,7 +60,8 @@ pbr_opts resolve_opts(const pbr_opts* o) {
 int check_opts(pbr_ctx* c, const pbr_opts& o) {
   if (!(o.tol > 0) || !(o.tol_inner > 0) || o.maxit_outer < 0 || o.maxit_inner < 1 ||
       o.ncv < 0 || (o.precond != 0 && o.precond != 1) || o.check_every < 0 ||
-      (o.concurrent != 0 && o.concurrent != 1) || (o.graphs != 0 && o.graphs != 1)) {
+      (o.concurrent != 0 && o.concurrent != 1) || (o.graphs != 0 && o.graphs != 1) ||
+      (o.warm_start != 0 && o.warm_start != 1)) {
     c->set_error("invalid pbr_opts");
     return ST_EINVAL;
   }
@@ -131,6 +132,7 @@ void pbr_opts_default(pbr_opts* o) {
   o->seed = 1;
   o->concurrent = 1;
   o->graphs = 1;
+  o->warm_start = 1;
 }
 
 pbr_status pbr_create(pbr_ctx** out, int n1, int n2, int n3, const double* A_lat, int hip_device,

@@ -57,6 +57,7 @@ struct LayoutWork {
   cplx *b = nullptr, *w = nullptr, *t = nullptr;   // Lanczos / staging vectors
   cplx *U = nullptr, *U2 = nullptr;                // Krylov bases (3N x ucols)
   int ucols = 0;
+  int ritz_n = 0;  // Ritz vectors (M^1/2-scaled) of the last finished run held in U2
   cplx* small = nullptr;      // small device matrices (h, Y), 4096 complex
   double* part = nullptr;     // reduction partials
   double* part2 = nullptr;
@@ -194,6 +195,7 @@ struct LayoutRef {
   int slot = 0;
   int block = -1;
   double kappa[3] = {0, 0, 0};
+  int warm_slot = -1;  // start from the Ritz vectors held by work area (warm_slot, block)
 };
 
 // Adds sum_s w[s] d lambda_s / d (C21, rho) of nvec M-normalised eigenvectors v

@@ -34,6 +34,7 @@ int ensure_basis(pbr_ctx* c, LayoutWork& W, int cols) {
   dev_free(W.U2);
   W.U = W.U2 = nullptr;
   W.ucols = 0;
+  W.ritz_n = 0;
   PBR_TRY(alloc_vec(c, &W.U, 3 * W.N * (long)cols));
   PBR_TRY(alloc_vec(c, &W.U2, 3 * W.N * (long)cols));
   W.ucols = cols;
@@ -529,10 +530,23 @@ int lz_start(pbr_ctx* c, LanczosRun& R, const LayoutRef& L, int nev, const pbr_o
   R.Yr.assign(2 * (size_t)m * m, 0.0);
   R.Hd.assign(2 * (size_t)m * m, 0.0);
   R.hbuf.assign(4 * m + 8, 0.0);
-  // start vector
+  // start vector: random, or the sum of the Ritz vectors a finished run of this
+  // layout kind left in a work area plus a random part of half that norm
   const hipStream_t SO = c->stream;
   int st_err;
   PBR_TRY(vec_random(c, SO, R.n3, (unsigned long long)(o.seed * 7919 + 17 + block), W.U));
+  if (o.warm_start && L.warm_slot >= 0) {
+    LayoutWork& S = c->wk(L.warm_slot, block);
+    const int nw = std::min(S.ritz_n, S.ucols);
+    if (nw > 0 && S.U2 && S.N == W.N) {
+      const double rn = vnorm(c, W, W.U, &st_err);
+      PBR_TRY(st_err);
+      PBR_TRY(vec_scale(c, SO, R.n3, W.U, 0.5 * std::sqrt((double)nw) / rn));
+      PBR_TRY(upload_small(c, W.small, std::vector<zc>(nw, zc(-1.0, 0.0))));
+      PBR_TRY(gemv_sub(c, SO, R.n3, nw, S.U2, R.ld, W.small, W.U));  // U += sum of columns
+    }
+  }
+  W.ritz_n = 0;  // this run now uses the work area
   if (R.gamma) PBR_TRY(project_null(c, W, W.U));
   const double nrm = vnorm(c, W, W.U, &st_err);
   PBR_TRY(st_err);
@@ -692,6 +706,8 @@ int lz_finish(pbr_ctx* c, LanczosRun& R, double* evals, cplx* evecs_dev, pbr_sta
   }
   std::sort(lam.begin(), lam.end());
   for (int i = 0; i < nout; ++i) evals[i] = lam[i].first;
+  // U2 keeps the Ritz vectors for a later warm start (unless reused below)
+  W.ritz_n = evecs_dev ? 0 : nout;
   if (evecs_dev) {
     // reorder columns to ascending eigenvalue
     bool sorted = true;
@@ -851,6 +867,9 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
           L[np].slot = q;
           L[np].block = b;
           for (int l = 0; l < 3; ++l) L[np].kappa[l] = kappas[3 * (k0 + q) + l];
+          // warm start: a re-solve from its own Ritz vectors, a first solve from
+          // those of the last wave vector of the previous group (same block)
+          L[np].warm_slot = round > 0 ? q : (k0 > 0 ? PBR_KSLOTS - 1 : -1);
           nevs[np] = nev_b[q][b];
           ev[np] = vals[q][b].data();
           qk[np] = q;
@@ -916,9 +935,10 @@ int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const 
 int full_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
               const pbr_opts& o, double* evals, pbr_stats* st) {
   int status = ST_OK;
-  const int group = o.concurrent ? PBR_KSLOTS : 1;
-  for (int k0 = 0; k0 < nk; k0 += group) {
-    const int gk = std::min(group, nk - k0);
+  // groups of PBR_KSLOTS wave vectors whether or not they run in lockstep, so the
+  // warm starts (and hence the results) are the same both ways
+  for (int k0 = 0; k0 < nk; k0 += PBR_KSLOTS) {
+    const int gk = std::min(PBR_KSLOTS, nk - k0);
     LayoutRef L[PBR_KSLOTS];
     int nevs[PBR_KSLOTS], rc[PBR_KSLOTS];
     double* ev[PBR_KSLOTS];
@@ -928,11 +948,18 @@ int full_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
       L[q].slot = q;
       L[q].block = -1;
       for (int l = 0; l < 3; ++l) L[q].kappa[l] = kappas[3 * (k0 + q) + l];
+      L[q].warm_slot = k0 > 0 ? PBR_KSLOTS - 1 : -1;
       nevs[q] = nev;
       ev[q] = evals + (long)(k0 + q) * nev;
       rc[q] = ST_OK;
     }
-    PBR_TRY(lanczos_batch(c, gk, L, nevs, shift, o, ev, nullptr, part, rc));
+    if (o.concurrent) {
+      PBR_TRY(lanczos_batch(c, gk, L, nevs, shift, o, ev, nullptr, part, rc));
+    } else {
+      for (int q = 0; q < gk; ++q)
+        PBR_TRY(lanczos_batch(c, 1, L + q, nevs + q, shift, o, ev + q, nullptr, part + q,
+                              rc + q));
+    }
     for (int q = 0; q < gk; ++q) {
       if (st) add_stats(st, part[q]);
       if (rc[q] == ST_ENOCONV) status = ST_ENOCONV;

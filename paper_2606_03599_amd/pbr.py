@@ -32,7 +32,8 @@ class PbrOpts(ctypes.Structure):
                 ("maxit_outer", ctypes.c_int), ("maxit_inner", ctypes.c_int),
                 ("ncv", ctypes.c_int), ("precond", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("seed", ctypes.c_int),
-                ("concurrent", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("concurrent", ctypes.c_int), ("graphs", ctypes.c_int),
+                ("warm_start", ctypes.c_int)]
 
 
 class PbrStats(ctypes.Structure):

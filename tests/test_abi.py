@@ -45,7 +45,7 @@ def test_opts_defaults(L):
     assert o.tol == 1e-12 and o.tol_inner == 1e-12
     assert o.maxit_outer == 300 and o.maxit_inner == 200
     assert o.precond == 1 and o.ncv == 0
-    assert o.concurrent == 1 and o.graphs == 1
+    assert o.concurrent == 1 and o.graphs == 1 and o.warm_start == 1
 
 
 def test_create_rejects_bad_sizes(L):
