@@ -13,26 +13,34 @@
 //
 // Kernel organisation (one fused pass, HBM-bound):
 //  * a work-group owns a TI x TJ tile of the (i, j) plane of the layout box and
-//    streams through a chunk of planes k in [k0, k1);
+//    streams through a chunk of planes k in [k0, k1); with TI x TJ = 16 x 13
+//    the own lanes and the ring lanes (below) fill four waves, one per SIMD, so
+//    a lane may hold up to 512 registers;
 //  * the velocity is staged in LDS once per plane for the tile and the ring its
-//    backward neighbours reach, in a rolling window of three planes (the
-//    loads of the next plane are issued first in a step, ahead of the stiffness
-//    prefetch, and stored at its end).  Staging
-//    multiplies every value by the Bloch phase of its (possibly out-of-box)
-//    position, i.e. it stores the extended field v(x + n_l e_l) = e^{i phi_l} v(x)
-//    of Eq. 3.2, so no later step needs wrap or phase logic;
+//    backward neighbours reach, in a ring of four planes; the loads of plane
+//    s+3 are issued at the top of step s into one of two alternating register
+//    sets and staged at the end of step s+1.  Staging multiplies every value by
+//    the Bloch phase of its (possibly out-of-box) position, i.e. it stores the
+//    extended field v(x + n_l e_l) = e^{i phi_l} v(x) of Eq. 3.2, so no later
+//    step needs wrap or phase logic;
+//  * the stiffness (21 entries) and rho of a plane come from the tiled layout
+//    of DevMaterial::Ct (22 x 16 doubles contiguous per row run), loaded two
+//    planes ahead into two alternating register sets: the set of plane s+2 is
+//    refilled right after the stress of plane s has consumed it;
 //  * for each plane s, tau is formed once per node of the tile plus the ring its
 //    forward neighbours reach (i+1 column, j-1 / j+TJ rows) -- one lane per
-//    position: the tile's lanes plus one extra wave for the ring -- from the
-//    staged velocity and the stiffness (prefetched one plane ahead in registers),
-//    and staged in LDS;
+//    position -- from the staged velocity and the stiffness, and staged in LDS;
+//    the shift term s rho x of an output node is added at the same time;
 //  * every output node adds the contributions of plane s to three rolling
 //    accumulators (planes s-1, s, s+1: a forward step changes k by -1, 0 or +1)
-//    and writes plane s-1, now complete, together with s rho x;
+//    and writes plane s-1, now complete;
 //  * ring positions no output of the tile reaches (parity-dependent in a block
 //    layout, where a step changes y2 by 0 or w2(i)) are skipped;
 //  * tiles are numbered so that consecutive tiles go to one XCD, keeping the
-//    ring re-reads of C and x in that XCD's L2;
+//    ring re-reads of C and x in that XCD's L2; the chunk length is autotuned
+//    per (batch size, box) among the best candidates of a cost model;
+//  * the (x, y) partials of the fused PCG are per tile and pair of planes, so
+//    no result depends on the chunking;
 //  * all global accesses are buffer loads/stores with 32-bit offsets (one
 //    descriptor per array, scalar plane offsets).
 #include <algorithm>
