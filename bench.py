@@ -397,6 +397,7 @@ def main():
                       "in one launch (as the blocked path runs it)",
             "algorithmic_bytes": b4_bytes, "avg_launch_us": round(t_b4 * 1e6, 2)}
     kernels = {"blocks4_matvec_us": round(t_b4 * 1e6, 2), "blocks4_matvec_GBps": round(b4_gbs, 1),
+               "blocks4_matvec_frac_copy": round(b4_gbs / cpeak, 4),
                "block_matvec_us": round(t_blk * 1e6, 2), "block_matvec_GBps": round(blk_gbs, 1),
                "block_matvec_frac_copy": round(blk_gbs / cpeak, 4),
                "full_matvec_us": round(t_full * 1e6, 2), "full_matvec_GBps": round(full_gbs, 1),
