@@ -72,6 +72,13 @@ struct ApplyArgs {
   double s;
   int tiles_i, tiles_j, chunk;
   int per;            // work-groups per layout
+  // Layouts that share a material (the same parity block at different wave
+  // vectors) sit next to each other in b[]: group g is b[gs[g] .. gs[g+1]).
+  // Work-groups are numbered (group, tile and chunk, member), so the members of
+  // a group stream the same stiffness at the same time on one XCD and all but
+  // the first find it in that XCD's L2.
+  int ngroups;
+  int gs[PBR_MAX_BATCH + 1];
   ApplyBlock b[PBR_MAX_BATCH];
 };
 
@@ -227,8 +234,12 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
   const int xcd = w % 8, slot = w / 8;
   const int logical =
       (xcd < rem ? xcd * (per8 + 1) : rem * (per8 + 1) + (xcd - rem) * per8) + slot;
-  const int blk = logical / A.per;
-  const int local = logical - blk * A.per;
+  int grp = 0;
+  while (grp + 1 < A.ngroups && logical >= A.gs[grp + 1] * A.per) ++grp;
+  const int gsize = A.gs[grp + 1] - A.gs[grp];
+  const int rel = logical - A.gs[grp] * A.per;
+  const int local = rel / gsize;
+  const int blk = A.gs[grp] + (rel - local * gsize);
   const ApplyBlock& P = A.b[blk];
   if (P.st && P.st->done) return;  // whole work-group
   Geo g = A.g;
@@ -633,9 +644,18 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
   const long tiles = (long)A.tiles_i * A.tiles_j;
   const long np = tiles * ((g.L3 + PART_G - 1) / PART_G);  // (x, y) partials per layout
   if (nparts) *nparts = (int)np;
-  for (int t = 0; t < nb; ++t) {
+  // layouts ordered by material (stable), grouped by equal material
+  int ord[PBR_MAX_BATCH];
+  for (int t = 0; t < nb; ++t) ord[t] = t;
+  std::stable_sort(ord, ord + nb, [&](int u, int v) { return L[u].block < L[v].block; });
+  A.ngroups = 0;
+  for (int t = 0; t < nb; ++t)
+    if (t == 0 || L[ord[t]].block != L[ord[t - 1]].block) A.gs[A.ngroups++] = t;
+  A.gs[A.ngroups] = nb;
+  for (int u = 0; u < nb; ++u) {
+    const int t = ord[u];
     const DevMaterial& M = c->material(L[t].block);
-    ApplyBlock& B = A.b[t];
+    ApplyBlock& B = A.b[u];
     B.x = L[t].x;
     B.y = L[t].y;
     B.Ct = M.Ct;
