@@ -18,9 +18,16 @@ sides.  The full-space form (one solve of 3n^3 unknowns per k) is then compared
 with the blocked form on every fourth path point (--full-every), same GPU, same
 tolerances.
 
+Material form: the two-phase cell has two distinct (C21, rho) rows, so by
+default the kernels read the palette form (one byte per node naming its row)
+instead of 21 stiffness entries and rho per node; --material-form dense forces
+the dense form.  Both give the same matvec bit for bit.
+
 Also measured live: the fused matvec (A + delta M) x of the four parity blocks
 in one launch (as the blocked path issues it; HIP events on the context stream),
-reported against the MI355X HBM peak as the roofline of the dominant kernel; one
+in the form the path runs and in the other form, reported against the MI355X
+HBM peak (algorithmic bytes: x, y and the material as that form stores it) as
+the roofline of the dominant kernel; one
 block per launch (rotating through the blocks), the full-space matvec and the
 block preconditioner beside it; and the oracle (CPU) cost of the same path
 estimated from a bounded sample (one oracle matvec + preconditioner application
@@ -37,7 +44,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE = 48 + 168 + 8 + 48   # x, C (21 doubles), rho, y
+BYTES_PER_NODE = 48 + 168 + 8 + 48   # x, C (21 doubles), rho, y (dense material form)
+PAL_BYTES_PER_NODE = 48 + 1 + 48     # x, palette row (one byte), y (palette form)
 PRECOND_BYTES_PER_NODE = 48 + 48     # r in, z out
 
 
@@ -63,6 +71,9 @@ def parse():
     p.add_argument("--matvec-only", action="store_true",
                    help="only the matvec timing (for hardware-counter runs)")
     p.add_argument("--mv-iters", type=int, default=100)
+    p.add_argument("--material-form", choices=("auto", "dense"), default="auto",
+                   help="auto: the kernels read the material's palette form when it has one "
+                        "(at most 256 distinct rows); dense: always the 21 + 1 doubles per node")
     p.add_argument("--serial-blocks", action="store_true",
                    help="solve the four blocks one after another instead of in lockstep")
     return p.parse_args()
@@ -364,6 +375,11 @@ def main():
     ctx = pbr.Context(dims, A_lat=A_lat)
     ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
     delta = ctx.default_shift()
+    pal_rows = ctx.palette_size()
+    if args.material_form == "dense":
+        ctx.set_palette(False)
+    form = "palette" if ctx.palette_size() > 0 else "dense"
+    log(f"material: {pal_rows} distinct rows, the kernels read the {form} form")
     if args.first > 0:
         kappas = kappas[:args.first]
     kap_mv = (0.15, 0.05, 0.10)
@@ -372,29 +388,38 @@ def main():
 
     # ---- matvec roofline (dominant kernel), live HIP-event timing ----
     t_b4 = blocks_timing(torch, ctx, n, kap_mv, delta, max(10, args.mv_iters // 2))
+    t_b4_other = None
+    if pal_rows > 0:  # the other form of the same launch, for comparison
+        ctx.set_palette(form == "dense")
+        t_b4_other = blocks_timing(torch, ctx, n, kap_mv, delta, max(10, args.mv_iters // 2))
+        ctx.set_palette(form == "palette")
     t_blk = kernel_timing(torch, ctx, n, kap_mv, delta, args.mv_iters, (0, 1, 2, 3), "apply")
     t_full = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 4), (-1,),
                            "apply")
     t_pc = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 2), (0, 1, 2, 3),
                          "precond")
     nb = n ** 3 // 4
-    b4_bytes = BYTES_PER_NODE * 4 * nb
+    bpn = PAL_BYTES_PER_NODE if form == "palette" else BYTES_PER_NODE
+    b4_bytes = bpn * 4 * nb
     b4_gbs = b4_bytes / t_b4 / 1e9
-    blk_bytes = BYTES_PER_NODE * nb
+    blk_bytes = bpn * nb
     blk_gbs = blk_bytes / t_blk / 1e9
-    full_gbs = BYTES_PER_NODE * n ** 3 / t_full / 1e9
+    full_gbs = bpn * n ** 3 / t_full / 1e9
     pc_gbs = PRECOND_BYTES_PER_NODE * nb / t_pc / 1e9
     cpeak = copy_peak(torch)
+    if t_b4_other is not None:
+        log(f"4-block matvec launch, other material form: {t_b4_other*1e6:.1f} us")
     log(f"4-block matvec launch {t_b4*1e6:.1f} us = {b4_gbs:.0f} GB/s; one block "
         f"{t_blk*1e6:.1f} us = {blk_gbs:.0f} GB/s; full {t_full*1e6:.1f} us = "
         f"{full_gbs:.0f} GB/s; block preconditioner {t_pc*1e6:.1f} us; copy {cpeak:.0f} GB/s")
     rec = traffic_record(os.path.join(ROOT, "paper_2606_03599_amd", "csrc", "stencil.hip"),
-                         f"matvec_blocks_n{n}_traffic")
+                         f"matvec_blocks_n{n}_{form}_traffic")
     roof = {"bound": "hbm", "achieved": round(b4_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(b4_gbs / HBM_PEAK_GBS, 4),
             "traffic": (None if rec is None else rec["hbm_bytes_per_launch"]),
             "kernel": "apply_stream_kernel: fused (A + delta M) x of the four parity blocks "
-                      "in one launch (as the blocked path runs it)",
+                      f"in one launch (as the blocked path runs it), {form} material form "
+                      f"({bpn} algorithmic bytes per node)",
             "algorithmic_bytes": b4_bytes, "avg_launch_us": round(t_b4 * 1e6, 2)}
     kernels = {"blocks4_matvec_us": round(t_b4 * 1e6, 2), "blocks4_matvec_GBps": round(b4_gbs, 1),
                "blocks4_matvec_frac_copy": round(b4_gbs / cpeak, 4),
@@ -404,7 +429,15 @@ def main():
                "full_matvec_frac_hbm": round(full_gbs / HBM_PEAK_GBS, 4),
                "block_precond_us": round(t_pc * 1e6, 2),
                "block_precond_GBps_algorithmic": round(pc_gbs, 1),
-               "copy_peak_GBps": round(cpeak, 1)}
+               "copy_peak_GBps": round(cpeak, 1), "material_form": form,
+               "material_rows": pal_rows}
+    if t_b4_other is not None:
+        obpn = BYTES_PER_NODE if form == "palette" else PAL_BYTES_PER_NODE
+        ogbs = obpn * 4 * nb / t_b4_other / 1e9
+        other = "dense" if form == "palette" else "palette"
+        kernels[f"blocks4_matvec_{other}_us"] = round(t_b4_other * 1e6, 2)
+        kernels[f"blocks4_matvec_{other}_GBps"] = round(ogbs, 1)
+        kernels[f"blocks4_matvec_{other}_frac_hbm"] = round(ogbs / HBM_PEAK_GBS, 4)
     if args.matvec_only:
         print(json.dumps({"roofline": roof, "kernels": kernels}), flush=True)
         ctx.close()

@@ -130,6 +130,28 @@ pbr_status pbr_create(pbr_ctx **out, int n1, int n2, int n3, const double *A_lat
 pbr_status pbr_set_material(pbr_ctx *c, const double *C21, const double *rho,
                             int on_device);
 
+/* Storage form of the nodewise material C_h, rho (Eq. 3.15) that the operator
+ * kernels read.  pbr_set_material always builds the dense form (21 stiffness
+ * entries and rho per node).  When the material has at most 256 distinct
+ * (C21, rho) rows, compared bit for bit, it also builds a palette form: the
+ * distinct rows once, plus one byte per node naming its row.  Both forms hold
+ * the same values: the operator's output (pbr_apply, pbr_apply_blocks) is
+ * bit-identical either way, while solver results agree to rounding, since the
+ * fused PCG sums its inner products per stencil tile and the two forms use
+ * different tiles.  The palette form reads about a third of the bytes per
+ * matvec.
+ *
+ * pbr_set_palette: enable = 1 (the default) lets the kernels read the palette
+ * form whenever it exists; 0 makes them read the dense form.  Takes effect at
+ * the next call, for the current and later materials.  PBR_EINVAL for a NULL
+ * context or enable other than 0 or 1.
+ *
+ * pbr_material_palette: number of palette rows the kernels read (1..256), 0 when
+ * they read the dense form (more than 256 distinct rows, or disabled), -1 for a
+ * NULL context or before pbr_set_material. */
+pbr_status pbr_set_palette(pbr_ctx *c, int enable);
+int pbr_material_palette(const pbr_ctx *c);
+
 /* Override the constant reference material of the preconditioner
  * (K(m) = Bhat(m) C_ref Bhat(m)^H + shift * rho_ref * I_3, Sec. 5.3-5.4): C21_ref
  * is 21 host doubles in the C21 order, rho_ref > 0. */

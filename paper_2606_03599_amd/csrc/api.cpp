@@ -221,7 +221,9 @@ void pbr_destroy(pbr_ctx* c) {
     dev_free(M.rho);
     dev_free(M.srho);
     dev_free(M.isrho);
+    dev_free(M.idx);
   }
+  dev_free(c->pal);
   for (auto& T : c->fft)
     for (int l = 0; l < 3; ++l) {
       dev_free(T.twist[l]);
@@ -306,6 +308,7 @@ pbr_status pbr_set_material(pbr_ctx* c, const double* C21, const double* rho, in
     W.nf = 0;
   }
   c->have_material = true;
+  ++c->mat_gen;
   return PBR_OK;
 }
 
@@ -317,7 +320,26 @@ pbr_status pbr_set_reference(pbr_ctx* c, const double* C21_ref, double rho_ref) 
   }
   std::memcpy(c->Cref, C21_ref, sizeof(c->Cref));
   c->rho_ref = rho_ref;
+  ++c->mat_gen;
   return PBR_OK;
+}
+
+pbr_status pbr_set_palette(pbr_ctx* c, int enable) {
+  if (!c) return PBR_EINVAL;
+  if (enable != 0 && enable != 1) {
+    c->set_error("enable must be 0 or 1");
+    return PBR_EINVAL;
+  }
+  if (c->use_palette != (enable == 1)) {
+    c->use_palette = enable == 1;
+    ++c->mat_gen;
+  }
+  return PBR_OK;
+}
+
+int pbr_material_palette(const pbr_ctx* c) {
+  if (!c || !c->have_material) return -1;
+  return c->use_palette ? c->npal : 0;
 }
 
 double pbr_default_shift(const pbr_ctx* c) {

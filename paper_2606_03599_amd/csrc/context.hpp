@@ -29,11 +29,19 @@
 // patch of nodes are then four 128-byte segments, and a row's 22 entries are
 // one contiguous 2.8 KB run of HBM.
 #define PBR_CT_W 16
+// Palette form of the same data: when the material has at most PBR_PAL_MAX
+// distinct (C21, rho) rows, every layout also holds one byte per node (its row
+// in the palette, layout order) and the context holds the palette, 22 doubles
+// per row in the order of Ct's entries.  The stencil then reads one byte per
+// node instead of 176 and takes the row from LDS; the values, and therefore
+// every operator output, are the same bit for bit.
+#define PBR_PAL_MAX 256
 
 struct DevMaterial {
   long N = 0;
   long ct_len = 0;          // doubles in Ct
   double* Ct = nullptr;     // stencil tiles (layout above)
+  unsigned char* idx = nullptr;  // [N] palette row of each node (valid when npal > 0)
   double* rho = nullptr;    // [N]
   double* srho = nullptr;   // [N]  sqrt(rho)
   double* isrho = nullptr;  // [N]  1/sqrt(rho)
@@ -81,7 +89,7 @@ struct pbr_ctx {
   int cus = 256;       // compute units of the device
   // stencil chunk lengths chosen by the autotuner, per (batch size, box)
   struct StencilTune {
-    int nb = 0, L1 = 0, L2 = 0, L3 = 0, chunk = 0;
+    int nb = 0, L1 = 0, L2 = 0, L3 = 0, pal = 0, chunk = 0;
   } stencil_tune[PBR_TUNE_SLOTS];
   int stencil_tune_next = 0;
   hipStream_t stream = nullptr;
@@ -93,6 +101,12 @@ struct pbr_ctx {
   double rho_ref = 1.0;
   std::vector<double> rho_host;   // natural order
   DevMaterial mat[5];  // index 0 = natural (full), 1..4 = blocks 0..3
+  int npal = 0;              // palette rows (0: the material has more than PBR_PAL_MAX)
+  double* pal = nullptr;     // PBR_PAL_MAX x 22 doubles on the device
+  bool use_palette = true;   // pbr_set_palette
+  // Bumped whenever the material, the reference material or the stiffness
+  // form changes: launch arguments captured in a graph depend on all three.
+  unsigned long mat_gen = 0;
   FftTables fft[2 * PBR_KSLOTS];     // [slot][natural, blocks]
   LayoutWork work[5 * PBR_KSLOTS];   // [slot][natural, block 0..3]
 
@@ -110,6 +124,7 @@ struct pbr_ctx {
     const void* b[PBR_MAX_BATCH] = {};
     const void* x[PBR_MAX_BATCH] = {};
     double shift = 0.0;
+    unsigned long mat_gen = 0;
   } pcg_graph;
   hipStream_t cap_stream = nullptr;  // capture stream (the context stream may be the null stream)
   bool graphs_broken = false;        // capture failed once: launch eagerly from then on

@@ -48,6 +48,13 @@ __global__ void repack_kernel(MapArgs m, int nplanes, const double* __restrict__
   for (int q = 0; q < nplanes; ++q) dst[q * m.nb + t] = src[q * m.n + x];
 }
 
+__global__ void repack_u8_kernel(MapArgs m, const unsigned char* __restrict__ src,
+                                 unsigned char* __restrict__ dst) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.nb) return;
+  dst[t] = src[block_to_natural(m.n1, m.n2, m.m2, m.a, m.c, t)];
+}
+
 __global__ void sqrt_kernel(long N, const double* __restrict__ rho, double* __restrict__ s,
                             double* __restrict__ is) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -93,14 +100,65 @@ __global__ void tile_kernel(int L1, int L2, int tiles, long len, long N,
 }
 
 int alloc_material(pbr_ctx* c, DevMaterial& M, long N, long ct_len) {
-  if (M.N == N && M.Ct) return ST_OK;
+  if (M.N == N && M.Ct && M.idx) return ST_OK;
   M.N = N;
   M.ct_len = ct_len;
   PBR_TRY(dev_alloc(c, (void**)&M.Ct, sizeof(double) * ct_len));
   PBR_TRY(dev_alloc(c, (void**)&M.rho, sizeof(double) * N));
   PBR_TRY(dev_alloc(c, (void**)&M.srho, sizeof(double) * N));
   PBR_TRY(dev_alloc(c, (void**)&M.isrho, sizeof(double) * N));
+  PBR_TRY(dev_alloc(c, (void**)&M.idx, (size_t)N));
   return ST_OK;
+}
+
+// Distinct (C21, rho) rows of the material, compared bit for bit, in order of
+// first appearance, and each node's row (natural order).  Returns false as soon
+// as a (PBR_PAL_MAX + 1)-th row appears.  Runs of equal rows are checked
+// against the previous node first; other rows go through a small open-address
+// hash table.
+bool build_palette(long n, const double* C21, const double* rho, std::vector<double>& pal,
+                   std::vector<unsigned char>& idx) {
+  constexpr int HS = 4 * PBR_PAL_MAX;  // power of two
+  int slot_row[HS];
+  for (int& v : slot_row) v = -1;
+  pal.clear();
+  idx.assign((size_t)n, 0);
+  double row[22];
+  int last = -1;
+  for (long x = 0; x < n; ++x) {
+    std::memcpy(row, C21 + (size_t)x * 21, 21 * sizeof(double));
+    row[21] = rho[x];
+    if (last >= 0 && std::memcmp(row, &pal[(size_t)last * 22], sizeof(row)) == 0) {
+      idx[x] = (unsigned char)last;
+      continue;
+    }
+    unsigned long long h = 0x9e3779b97f4a7c15ULL;
+    for (int q = 0; q < 22; ++q) {
+      unsigned long long b;
+      std::memcpy(&b, &row[q], 8);
+      h = (h ^ b) * 0xff51afd7ed558ccdULL;
+      h ^= h >> 29;
+    }
+    int sl = (int)(h & (HS - 1));
+    int found = -1;
+    while (slot_row[sl] >= 0) {
+      if (std::memcmp(row, &pal[(size_t)slot_row[sl] * 22], sizeof(row)) == 0) {
+        found = slot_row[sl];
+        break;
+      }
+      sl = (sl + 1) & (HS - 1);
+    }
+    if (found < 0) {
+      const int np = (int)(pal.size() / 22);
+      if (np == PBR_PAL_MAX) return false;
+      pal.insert(pal.end(), row, row + 22);
+      slot_row[sl] = np;
+      found = np;
+    }
+    idx[x] = (unsigned char)found;
+    last = found;
+  }
+  return true;
 }
 
 // Tiles of one layout from its stiffness planes and rho.
@@ -143,8 +201,13 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
   // natural planes (and one block's planes) live only during the upload
   double* tmp = nullptr;
   double* tmpb = nullptr;
+  std::vector<double> hpal;
+  std::vector<unsigned char> hidx;
+  const bool fits = build_palette(n, C21, rho, hpal, hidx);
+  c->npal = 0;
   int st = dev_alloc(c, (void**)&tmp, sizeof(double) * 21 * n);
   if (st == ST_OK && c->even) st = dev_alloc(c, (void**)&tmpb, sizeof(double) * 21 * (n / 4));
+  if (st == ST_OK && fits) st = dev_alloc(c, (void**)&c->pal, sizeof(double) * PBR_PAL_MAX * 22);
   auto run = [&]() -> int {
     PBR_HIP(c, hipMemcpyAsync(tmp, planes.data(), sizeof(double) * 21 * n, hipMemcpyHostToDevice,
                               c->stream));
@@ -153,6 +216,11 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
                        F.srho, F.isrho);
     launch_tile(c, c->n1, c->n2, c->n3, tmp, F);
     PBR_HIP(c, hipGetLastError());
+    if (fits) {
+      PBR_HIP(c, hipMemcpyAsync(c->pal, hpal.data(), sizeof(double) * hpal.size(),
+                                hipMemcpyHostToDevice, c->stream));
+      PBR_HIP(c, hipMemcpyAsync(F.idx, hidx.data(), (size_t)n, hipMemcpyHostToDevice, c->stream));
+    }
     if (c->even) {
       for (int b = 0; b < 4; ++b) {
         DevMaterial& B = c->mat[b + 1];
@@ -166,6 +234,9 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
         hipLaunchKernelGGL(sqrt_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream, nb,
                            B.rho, B.srho, B.isrho);
         launch_tile(c, c->n1, c->n2 / 2, c->n3 / 2, tmpb, B);
+        if (fits)
+          hipLaunchKernelGGL(repack_u8_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, c->stream,
+                             m, (const unsigned char*)F.idx, B.idx);
         PBR_HIP(c, hipGetLastError());
       }
     }
@@ -178,6 +249,7 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
   dev_free(tmpb);
   if (st != ST_OK) return st;
   PBR_HIP(c, e);
+  c->npal = fits ? (int)(hpal.size() / 22) : 0;
   return ST_OK;
 }
 

@@ -269,7 +269,8 @@ template <class F>
 int ensure_pcg_graph(pbr_ctx* c, int nb, const LayoutRef* L, const cplx* const* b,
                      cplx* const* x, double shift, int chunk, F&& iterate) {
   pbr_ctx::PcgGraph& G = c->pcg_graph;
-  bool same = G.exec && G.nb == nb && G.chunk == chunk && G.shift == shift;
+  bool same = G.exec && G.nb == nb && G.chunk == chunk && G.shift == shift &&
+              G.mat_gen == c->mat_gen;
   for (int t = 0; same && t < nb; ++t)
     same = G.blocks[t] == L[t].block && G.slots[t] == L[t].slot && G.b[t] == b[t] &&
            G.x[t] == x[t] && G.kap[t][0] == L[t].kappa[0] && G.kap[t][1] == L[t].kappa[1] &&
@@ -309,6 +310,7 @@ int ensure_pcg_graph(pbr_ctx* c, int nb, const LayoutRef* L, const cplx* const* 
   G.nb = nb;
   G.chunk = chunk;
   G.shift = shift;
+  G.mat_gen = c->mat_gen;
   for (int t = 0; t < nb; ++t) {
     G.blocks[t] = L[t].block;
     G.slots[t] = L[t].slot;

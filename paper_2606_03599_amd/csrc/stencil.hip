@@ -58,6 +58,7 @@ struct ApplyBlock {
   const cplx* x;
   cplx* y;
   const double* Ct;      // stiffness and rho tiles of the layout (DevMaterial::Ct)
+  const unsigned char* idx;  // palette row of each node (DevMaterial::idx), palette form
   const PcgScalars* st;  // optional: this block's work-groups return once st->done != 0
   double* part;          // optional: per-work-group partials of Re(x^H y)
   int a, c;              // class bits of the block (unused in the natural layout)
@@ -69,6 +70,8 @@ struct ApplyArgs {
   int N;              // nodes of one layout (all offsets below fit in 32 bits)
   int ct_tiles;       // runs of PBR_CT_W nodes per row of the stiffness tiles
   int ct_bytes;       // bytes of one layout's stiffness tiles
+  const double* pal;  // palette form: npal rows of 22 doubles (C21, rho)
+  int npal;
   double s;
   int tiles_i, tiles_j, chunk;
   int per;            // work-groups per layout
@@ -95,6 +98,9 @@ __device__ inline double ldd(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
 }
 __device__ inline cplx ldc(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return __builtin_bit_cast(cplx, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ inline int ldb(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b8(r, voff, soff, 0);
 }
 __device__ inline void stc(__amdgpu_buffer_rsrc_t r, cplx v, int voff, int soff) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
@@ -212,9 +218,10 @@ __host__ __device__ constexpr int tile_threads(int TI, int TJ) {
 constexpr int PART_G = 2;
 
 // Work-group layout: own lanes, then ring lanes, then idle lanes up to a wave.
-template <int TI, int TJ>
+template <int TI, int TJ, bool PAL>
 __global__ void __launch_bounds__(tile_threads(TI, TJ))
-    __attribute__((amdgpu_waves_per_eu(1, 1))) apply_stream_kernel(ApplyArgs A) {
+    __attribute__((amdgpu_waves_per_eu(PAL ? 2 : 1, PAL ? 2 : 1)))
+    apply_stream_kernel(ApplyArgs A) {
   constexpr int PI = TI + 1, PJ = TJ + 2, NP = PI * PJ;  // tau region
   constexpr int XI = TI + 2, XJ = TJ + 4, NX = XI * XJ;  // velocity region
   constexpr int NOWN = TI * TJ;
@@ -225,6 +232,7 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
   __shared__ cplx tau_s[6 * NP];
   __shared__ cplx x_s[4][3 * NX];
   __shared__ double red[NT / 64 + 1];
+  extern __shared__ cplx pal_s[];  // palette form: npal rows of 11 pairs (dynamic LDS)
 
   // XCD-aware numbering: work-groups are dealt round-robin over 8 XCDs, so
   // give each XCD a contiguous range of (layout, tile, chunk) indices.
@@ -253,6 +261,7 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
   const __amdgpu_buffer_rsrc_t rx = rsrc(P.x, (unsigned)N * 48u);
   const __amdgpu_buffer_rsrc_t ry = rsrc(P.y, (unsigned)N * 48u);
   const __amdgpu_buffer_rsrc_t rc = rsrc(P.Ct, (unsigned)A.ct_bytes);
+  const __amdgpu_buffer_rsrc_t ri = rsrc(P.idx, PAL ? (unsigned)N : 0u);
   const int cs = N * 16;
   const int ntile = A.tiles_i * A.tiles_j;
   const int tile = local % ntile;
@@ -350,6 +359,22 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
 #pragma unroll
     for (int q = 0; q < 22; ++q) Cz[q] = ldd(rc, o8, q * PBR_CT_W * 8);
   };
+  // palette form: the node's palette row of a tau plane (one byte), and the
+  // row itself from LDS into a register set when the stress needs it
+  auto load_I = [&](int s, bool need, int& I) {
+    int qk;
+    const int kk = wrapq(s, L3, qk);
+    I = ldb(ri, need ? ai + L1 * (aj + L2 * kk) : OOB, 0);
+  };
+  auto fetch_pal = [&](int I, double Cz[22]) {
+    const cplx* row = pal_s + min(I, A.npal - 1) * 11;
+#pragma unroll
+    for (int q = 0; q < 11; ++q) {
+      const cplx v = row[q];
+      Cz[2 * q] = v.x;
+      Cz[2 * q + 1] = v.y;
+    }
+  };
 
   // ---- output (own lanes) ----
   const int io = vi, jo = vj;
@@ -390,6 +415,7 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
   cplx XA[XPASS][3], XB[XPASS][3];
   bool need_a = needed_at(k0 - 1), need_b = needed_at(k0);
   double Ca[22], Cb[22];
+  int Ia = 0, Ib = 0;  // palette form: rows of the two tau planes in flight
   {
     cplx X0[XPASS][3], X1[XPASS][3];
     stage_load(k0 - 2, true, X0);
@@ -397,10 +423,17 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
     stage_load(k0, true, XA);
     stage_load(k0 + 1, k0 + 1 <= k1 + 1, XB);
     __builtin_amdgcn_sched_barrier(0);
-    load_C(k0 - 1, need_a, Ca);
-    // keep the two sets in issue order: the loop's waits count on it
-    __builtin_amdgcn_sched_barrier(0);
-    load_C(k0, need_b, Cb);
+    if constexpr (PAL) {
+      load_I(k0 - 1, need_a, Ia);
+      load_I(k0, need_b, Ib);
+      for (int e = tid; e < A.npal * 11; e += NT)
+        pal_s[e] = mk(A.pal[2 * e], A.pal[2 * e + 1]);
+    } else {
+      load_C(k0 - 1, need_a, Ca);
+      // keep the two sets in issue order: the loop's waits count on it
+      __builtin_amdgcn_sched_barrier(0);
+      load_C(k0, need_b, Cb);
+    }
     stage_store(k0 - 2, X0);
     stage_store(k0 - 1, X1);
     stage_store(k0, XA);
@@ -413,7 +446,7 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
   const double shift = A.s;
   __syncthreads();
 
-#define PBR_STEP(S_, Cuse, need_use, Xload, Xstore)                                   \
+#define PBR_STEP(S_, Cuse, Iuse, need_use, Xload, Xstore)                             \
   do {                                                                                \
     const int s = (S_);                                                               \
     finish_part();                                                                    \
@@ -421,6 +454,7 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
     /* ---- tau of plane s from the staged velocity ---- */                           \
     const cplx* xs0 = x_s[wslot(s)];                                                  \
     if (need_use) {                                                                   \
+      if constexpr (PAL) fetch_pal(Iuse, Cuse);                                       \
       /* velocity at the node and its four backward neighbours: all fifteen LDS */    \
       /* reads are issued together, then the gradient G[m][a] = D'_m^H v_a; */        \
       /* own nodes of an output plane also take the shift term s rho x here */        \
@@ -455,7 +489,10 @@ _Pragma("unroll")                                                               
     }                                                                                 \
     /* stiffness of plane s+2 into the registers just consumed */                    \
     need_use = (s + 2 <= k1) && needed_at(s + 2);                                     \
-    load_C(s + 2, need_use, Cuse);                                                    \
+    if constexpr (PAL)                                                                \
+      load_I(s + 2, need_use, Iuse);                                                  \
+    else                                                                              \
+      load_C(s + 2, need_use, Cuse);                                                  \
     __syncthreads();                                                                  \
     /* ---- consume plane s ---- */                                                   \
     const int t = s - 1; /* output plane completed in this step */                    \
@@ -532,14 +569,23 @@ _Pragma("unroll")                                                               
   } while (0)
 
   for (int s0 = k0 - 1; s0 <= k1; s0 += 2) {
-    PBR_STEP(s0, Ca, need_a, XA, XB);
-    if (s0 + 1 <= k1) PBR_STEP(s0 + 1, Cb, need_b, XB, XA);
+    PBR_STEP(s0, Ca, Ia, need_a, XA, XB);
+    if (s0 + 1 <= k1) PBR_STEP(s0 + 1, Cb, Ib, need_b, XB, XA);
   }
 #undef PBR_STEP
   finish_part();
 }
 
 constexpr int TILE_I = 16, TILE_J = 13;
+// Palette form: without the stiffness stream the kernel waits on LDS and
+// barriers rather than HBM, so it takes a tile whose LDS (73 KB plus the
+// palette) lets two work-groups share a CU.
+constexpr int TILE_J_PAL = 11;
+constexpr int pal_lds_bytes(int npal) { return npal * 11 * 16; }
+// LDS of the palette form's static arrays (x ring, tau, reduction slots)
+constexpr int PAL_STATIC_LDS = 4 * 3 * (TILE_I + 2) * (TILE_J_PAL + 4) * 16 +
+                               6 * (TILE_I + 1) * (TILE_J_PAL + 2) * 16 +
+                               (tile_threads(TILE_I, TILE_J_PAL) / 64 + 1) * 8;
 
 }  // namespace
 
@@ -555,13 +601,15 @@ constexpr int TILE_I = 16, TILE_J = 13;
 // own (same inputs, same outputs, rewritten), and since the (x, y) partials are
 // per tile and group no result depends on which chunk wins.
 template <class F>
-int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, long tiles, F&& launch, int* out) {
+int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, int pal, int per_cu, long tiles, F&& launch,
+                int* out) {
   for (const auto& e : c->stencil_tune)
-    if (e.nb == nb && e.L1 == g.L1 && e.L2 == g.L2 && e.L3 == g.L3 && e.chunk > 0) {
+    if (e.nb == nb && e.L1 == g.L1 && e.L2 == g.L2 && e.L3 == g.L3 && e.pal == pal &&
+        e.chunk > 0) {
       *out = e.chunk;
       return ST_OK;
     }
-  const int cus = std::max(1, c->cus);
+  const int cus = std::max(1, c->cus) * per_cu;  // work-groups resident at once
   std::vector<std::pair<long, int>> cand;  // (model cost, chunk)
   for (int ch = std::min(PART_G, g.L3); ch <= g.L3; ++ch) {
     if (ch % PART_G != 0 && ch != g.L3) continue;
@@ -604,20 +652,27 @@ int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, long tiles, F&& launch, int* o
   slot.L1 = g.L1;
   slot.L2 = g.L2;
   slot.L3 = g.L3;
+  slot.pal = pal;
   slot.chunk = *out;
   return ST_OK;
 }
 
+// Whether the material's palette form is the one the stencil reads.
+static int apply_palette(const pbr_ctx* c) { return c->use_palette && c->npal > 0 ? 1 : 0; }
+
 bool apply_tuned(const pbr_ctx* c, const Geo& g, int nb) {
+  const int pal = apply_palette(c);
   for (const auto& e : c->stencil_tune)
-    if (e.nb == nb && e.L1 == g.L1 && e.L2 == g.L2 && e.L3 == g.L3 && e.chunk > 0) return true;
+    if (e.nb == nb && e.L1 == g.L1 && e.L2 == g.L2 && e.L3 == g.L3 && e.pal == pal &&
+        e.chunk > 0)
+      return true;
   return false;
 }
 
 long apply_partials(const pbr_ctx* c, int block) {
   const long L1 = c->n1, L2 = block < 0 ? c->n2 : c->n2 / 2, L3 = block < 0 ? c->n3 : c->n3 / 2;
-  return ((L1 + TILE_I - 1) / TILE_I) * ((L2 + TILE_J - 1) / TILE_J) *
-         ((L3 + PART_G - 1) / PART_G);
+  const long tj = std::max((L2 + TILE_J - 1) / TILE_J, (L2 + TILE_J_PAL - 1) / TILE_J_PAL);
+  return ((L1 + TILE_I - 1) / TILE_I) * tj * ((L3 + PART_G - 1) / PART_G);
 }
 
 int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, double s,
@@ -638,9 +693,13 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
   A.N = (int)Nl;
   A.ct_tiles = ct_tiles;
   A.ct_bytes = (int)(ct_len * 8);
+  const int pal = apply_palette(c);
+  A.pal = c->pal;
+  A.npal = c->npal;
   A.s = s;
   A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
-  A.tiles_j = (g.L2 + TILE_J - 1) / TILE_J;
+  const int tj = pal ? TILE_J_PAL : TILE_J;
+  A.tiles_j = (g.L2 + tj - 1) / tj;
   const long tiles = (long)A.tiles_i * A.tiles_j;
   const long np = tiles * ((g.L3 + PART_G - 1) / PART_G);  // (x, y) partials per layout
   if (nparts) *nparts = (int)np;
@@ -659,6 +718,7 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
     B.x = L[t].x;
     B.y = L[t].y;
     B.Ct = M.Ct;
+    B.idx = M.idx;
     B.st = L[t].st;
     B.part = L[t].part;
     B.a = L[t].block >= 0 ? L[t].block >> 1 : 0;
@@ -673,13 +733,20 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
     A.chunk = chunk;
     A.per = (int)(tiles * ((g.L3 + chunk - 1) / chunk));
     const unsigned grid = (unsigned)((long)A.per * nb);
-    hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J>), dim3(grid),
-                       dim3(tile_threads(TILE_I, TILE_J)), 0, c->stream, A);
+    if (pal)
+      hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J_PAL, true>), dim3(grid),
+                         dim3(tile_threads(TILE_I, TILE_J_PAL)), pal_lds_bytes(c->npal),
+                         c->stream, A);
+    else
+      hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J, false>), dim3(grid),
+                         dim3(tile_threads(TILE_I, TILE_J)), 0, c->stream, A);
     PBR_HIP(c, hipGetLastError());
     return ST_OK;
   };
   int chunk = 0;
-  PBR_TRY(tuned_chunk(c, g, nb, tiles, launch, &chunk));
+  const int per_cu =
+      pal && 2 * (PAL_STATIC_LDS + 256 + pal_lds_bytes(c->npal)) <= 160 * 1024 ? 2 : 1;
+  PBR_TRY(tuned_chunk(c, g, nb, pal, per_cu, tiles, launch, &chunk));
   return launch(chunk);
 }
 

@@ -67,6 +67,8 @@ _SIGS = {
                                   _dp, ctypes.c_int, _vp]),
     "pbr_set_material": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     "pbr_set_reference": (ctypes.c_int, [_vp, _dp, ctypes.c_double]),
+    "pbr_set_palette": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pbr_material_palette": (ctypes.c_int, [_vp]),
     "pbr_default_shift": (ctypes.c_double, [_vp]),
     "pbr_block_dim": (ctypes.c_long, [_vp, ctypes.c_int]),
     "pbr_block_gather": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]),
@@ -199,6 +201,14 @@ def pbr_set_reference(ctx, C21_ref, rho_ref):
 
 def pbr_default_shift(ctx):
     return lib().pbr_default_shift(ctx)
+
+
+def pbr_set_palette(ctx, enable):
+    _check(ctx, lib().pbr_set_palette(ctx, int(enable)))
+
+
+def pbr_material_palette(ctx):
+    return lib().pbr_material_palette(ctx)
 
 
 def pbr_block_dim(ctx, block):
@@ -399,6 +409,14 @@ class Context:
 
     def default_shift(self):
         return pbr_default_shift(self.h)
+
+    def set_palette(self, enable):
+        """Let the kernels read the material's palette form (True) or the dense form."""
+        pbr_set_palette(self.h, 1 if enable else 0)
+
+    def palette_size(self):
+        """Palette rows the kernels read; 0 for the dense form."""
+        return pbr_material_palette(self.h)
 
     def block_dim(self, block):
         return pbr_block_dim(self.h, block)

@@ -61,6 +61,8 @@ def test_create_rejects_bad_sizes(L):
 def test_null_context_calls_fail_cleanly(L):
     assert L.pbr_block_dim(None, 0) == -1
     assert L.pbr_default_shift(None) < 0
+    assert L.pbr_material_palette(None) == -1
+    assert L.pbr_set_palette(None, 1) == -1  # PBR_EINVAL
     L.pbr_destroy(None)
 
 
