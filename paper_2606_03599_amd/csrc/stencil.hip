@@ -27,6 +27,13 @@
 //    of DevMaterial::Ct (22 x 16 doubles contiguous per row run), loaded two
 //    planes ahead into two alternating register sets: the set of plane s+2 is
 //    refilled right after the stress of plane s has consumed it;
+//  * palette form (a material with at most PBR_PAL_MAX distinct rows): the
+//    same kernel reads instead one byte per node (its row), two planes ahead,
+//    and takes the row's 22 doubles from a copy of the palette in LDS when the
+//    stress needs them.  With the stiffness stream gone the kernel waits on
+//    LDS, barriers and instruction latency rather than HBM, so this variant
+//    uses a 16 x 11 tile (73 KB of LDS plus the palette) and a 256-register
+//    budget, and two work-groups share a CU;
 //  * for each plane s, tau is formed once per node of the tile plus the ring its
 //    forward neighbours reach (i+1 column, j-1 / j+TJ rows) -- one lane per
 //    position -- from the staged velocity and the stiffness, and staged in LDS;
@@ -589,14 +596,16 @@ constexpr int PAL_STATIC_LDS = 4 * 3 * (TILE_I + 2) * (TILE_J_PAL + 4) * 16 +
 
 }  // namespace
 
-// Chunk length of a launch.  One work-group fits a CU at a time (LDS and
-// registers), so a launch runs in ceil(work-groups / CUs) rounds, each as long
+// Chunk length of a launch.  One work-group of the dense form fits a CU at a
+// time (two of the palette form when its palette is small), so a launch runs
+// in ceil(work-groups / resident work-groups) rounds, each as long
 // as its longest chunk plus its start-up (the two partial planes a chunk
 // computes at its ends and the first loads, which nothing overlaps); the model
 // cost rounds x (chunk + 4) ranks the chunk lengths that are whole groups of
 // PART_G planes (or the whole box).  The autotuner times the four best of
-// them with real launches the first time a (batch size, box) is seen outside
-// stream capture, and keeps the fastest in the context; during capture, or
+// them with real launches the first time a (batch size, box, material form) is
+// seen outside stream capture, and keeps the fastest (a candidate replaces the
+// model's choice only if it is 5% faster) in the context; during capture, or
 // when timing fails, the model's best is used.  The launches are the caller's
 // own (same inputs, same outputs, rewritten), and since the (x, y) partials are
 // per tile and group no result depends on which chunk wins.
@@ -637,7 +646,10 @@ int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, int pal, int per_cu, long tile
              hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.0f;
         ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-        if (ok && r == 1 && (best_ms < 0.0f || ms < best_ms)) {
+        // another candidate must beat the model's choice clearly: candidates of
+        // equal model cost often time within noise of each other, and a stable
+        // choice keeps the launch (and its partials) the same from run to run
+        if (ok && r == 1 && (best_ms < 0.0f || ms < 0.95f * best_ms)) {
           best_ms = ms;
           *out = cand[k].second;
         }
