@@ -1,7 +1,7 @@
 """The paper's FCC workload (quartz matrix, silicon sphere, FCC lattice, Sec. 7)
 through the GPU eigensolver vs the dense oracle on small grids, including grid
 lengths with a factor 5 (radix-5 transforms of the preconditioner).
-Tolerance: 1e-9 relative on eigenvalues (the spec eigenvalue target)."""
+Tolerance: 1e-9 relative on eigenvalues (the eigenvalue accuracy target)."""
 
 import numpy as np
 import pytest
