@@ -112,17 +112,21 @@ def test_palette_size_rules():
 
 
 def test_palette_n128_four_blocks_bit_identical():
-    """The benchmark launch (four blocks, n = 128, two-phase cell): palette and
-    dense forms give the same output bit for bit, the palette's chunk length
-    autotuned on its own."""
+    """The benchmark launch (four blocks in one launch, n = 128, two-phase cell,
+    the bench's wave vector and shift): palette and dense forms give the same
+    output bit for bit, each form's chunk length autotuned on its own, and the
+    output matches the oracle on sampled nodes of every block."""
+    from oracle import pointwise as P
     dims = (128, 128, 128)
     log("palette n=128 four blocks")
     C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
     ctx = make_ctx(dims, C21, rho)
     assert ctx.palette_size() == 2
     n = 128 ** 3
-    x = to_dev(complex_gaussian(3 * n, seed=21))
-    kap, s = (0.25, 0.0, 0.125), D.default_shift(C21)
+    xf = complex_gaussian(3 * n, seed=21)
+    xs = [Bk.gather(xf, dims, b) for b in range(4)]
+    x = to_dev(np.concatenate(xs))
+    kap, s = (0.15, 0.05, 0.10), D.default_shift(C21)
     outs = {}
     for enable in (True, False, True):
         ctx.set_palette(enable)
@@ -130,6 +134,19 @@ def test_palette_n128_four_blocks_bit_identical():
             to_host(ctx.apply_blocks(kap, s, x, to_dev(np.zeros(3 * n, complex)))))
     assert np.array_equal(outs[True][0], outs[False][0])
     assert np.array_equal(outs[True][1], outs[False][0])
+    rng = np.random.default_rng(11)
+    pts = [tuple(int(v) for v in rng.integers(0, 128, 3)) for _ in range(32)]
+    pts += [(0, 0, 0), (127, 127, 127), (1, 0, 127), (126, 127, 0), (64, 63, 64)]
+    y_pts = P.apply_A_at(pts, xf, dims, kap, C21, rho, s=s)
+    idx = [p[0] + 128 * (p[1] + 128 * p[2]) for p in pts]
+    cls = Bk.node_class(dims)
+    nb3 = 3 * n // 4
+    for b in range(4):
+        Yb = outs[True][0][b * nb3:(b + 1) * nb3].reshape(3, -1)
+        pos = {int(v): t for t, v in enumerate(Bk.block_nodes(dims, b))}
+        sel = [t for t in range(len(pts)) if cls[idx[t]] == b]
+        got = np.array([Yb[:, pos[idx[t]]] for t in sel])
+        assert rel(got, y_pts[sel]) <= TOL, b
     ctx.close()
 
 
