@@ -372,38 +372,50 @@ struct SolveArgs {
   } b[PBR_MAX_BATCH];   // layout blockIdx.y of the batch
 };
 
-// K(m)^-1 b for the mode whose one-step phases are Ea = e^{i alpha},
+// Symbols of D'_m for the mode whose one-step phases are Ea = e^{i alpha},
 // Eb = e^{i beta}, Eg = e^{i gamma}: the diagonal shifts have symbols
-// e^{i(alpha +- beta +- gamma)} (Eq. 4.1).
-__device__ inline void mode_solve(const SolveArgs& S, cplx Ea, cplx Eb, cplx Eg, const cplx b[3],
-                                  cplx x[3]) {
+// e^{i(alpha +- beta +- gamma)} (Eq. 4.1), so e_m = cf[m][0] + h_m with
+// h_m = sum_{d>0} cf[m][d] sd_d linear in Ea; the mode with -Ea (m1 + n/2 in a
+// block's orbit) has e_m = cf[m][0] - h_m.  (The factors -i of the symbols
+// cancel in Bhat C Bhat^H.)
+__device__ inline void mode_half_symbols(const SolveArgs& S, cplx Ea, cplx Eb, cplx Eg,
+                                         cplx h[3]) {
   const cplx ab = cmul(Ea, Eb), abc = cmulc(Eb, Ea);  // e^{i(a+b)}, e^{i(a-b)}
-  cplx sd[5];
-  sd[0] = mk(1.0, 0.0);
-  sd[1] = cmul(ab, Eg);
-  sd[2] = cmulc(Eg, ab);
-  sd[3] = cmul(abc, Eg);
-  sd[4] = cmulc(Eg, abc);
-  // symbols of D'_m (the factors -i cancel in Bhat C Bhat^H)
-  cplx e[3];
+  cplx sd[4];
+  sd[0] = cmul(ab, Eg);
+  sd[1] = cmulc(Eg, ab);
+  sd[2] = cmul(abc, Eg);
+  sd[3] = cmulc(Eg, abc);
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     cplx acc = mk(0, 0);
 #pragma unroll
-    for (int d = 0; d <= 4; ++d) acc = cfma(S.cf[m][d], sd[d], acc);
-    e[m] = acc;
+    for (int d = 1; d <= 4; ++d) acc = cfma(S.cf[m][d], sd[d - 1], acc);
+    h[m] = acc;
   }
+}
+
+// x = K^-1 b, K = Bhat C_ref Bhat^H + shift rho_ref I_3 for the symbols e
+// (Sec. 5.3-5.4).  K is Hermitian positive definite; it is inverted through
+// its adjugate (one division, no square roots).
+__device__ inline void symbol_solve(const SolveArgs& S, const cplx e[3], const cplx b[3],
+                                    cplx x[3]) {
   // K = Bhat C Bhat^H with Bhat's rows (Voigt columns, symbol) sparse:
   //   u1: (11, e1) (13, e3) (12, e2);  u2: (22, e2) (23, e3) (12, e1);
   //   u3: (33, e3) (23, e2) (13, e1)
   // so K[r][c] = sum over the 3 x 3 pairs of C[k][l] e_a conj(e_b).
   constexpr int VK[3][3] = {{0, 4, 5}, {1, 3, 5}, {2, 3, 4}};  // Voigt columns of row r
   constexpr int VE[3][3] = {{0, 2, 1}, {1, 2, 0}, {2, 1, 0}};  // symbol index of each
-  cplx G[3][3];  // G[a][b] = e_a conj(e_b)
+  cplx G[3][3];  // G[a][b] = e_a conj(e_b) = conj(G[b][a])
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a) {
+    G[a][a] = mk(e[a].x * e[a].x + e[a].y * e[a].y, 0.0);
 #pragma unroll
-    for (int b2 = 0; b2 < 3; ++b2) G[a][b2] = cmulc(e[b2], e[a]);
+    for (int b2 = a + 1; b2 < 3; ++b2) {
+      G[a][b2] = cmulc(e[b2], e[a]);
+      G[b2][a] = cconj(G[a][b2]);
+    }
+  }
   cplx K[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -420,24 +432,22 @@ __device__ inline void mode_solve(const SolveArgs& S, cplx Ea, cplx Eb, cplx Eg,
           acc = cfma(cv, G[VE[r][u]][VE[col][v]], acc);
         }
       K[r][col] = acc;
-      K[col][r] = cconj(acc);
     }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) K[r][r].x += S.shift_rho;
-  // Cholesky K = L L^H and the two triangular solves
-  const double l00 = sqrt(K[0][0].x);
-  const cplx l10 = cscale(1.0 / l00, K[1][0]);
-  const cplx l20 = cscale(1.0 / l00, K[2][0]);
-  const double l11 = sqrt(K[1][1].x - (l10.x * l10.x + l10.y * l10.y));
-  const cplx l21 = cscale(1.0 / l11, csub(K[2][1], cmul(l20, cconj(l10))));
-  const double l22 =
-      sqrt(K[2][2].x - (l20.x * l20.x + l20.y * l20.y) - (l21.x * l21.x + l21.y * l21.y));
-  const cplx y0 = cscale(1.0 / l00, b[0]);
-  const cplx y1 = cscale(1.0 / l11, csub(b[1], cmul(l10, y0)));
-  const cplx y2 = cscale(1.0 / l22, csub(csub(b[2], cmul(l20, y0)), cmul(l21, y1)));
-  x[2] = cscale(1.0 / l22, y2);
-  x[1] = cscale(1.0 / l11, csub(y1, cmulc(l21, x[2])));
-  x[0] = cscale(1.0 / l00, csub(csub(y0, cmulc(l10, x[1])), cmulc(l20, x[2])));
+  // K = [[a, d, e], [conj d, bb, f], [conj e, conj f, c]]; K^-1 = adj(K) / det K
+  const double a = K[0][0].x + S.shift_rho, bb = K[1][1].x + S.shift_rho,
+               c = K[2][2].x + S.shift_rho;
+  const cplx d = K[0][1], ee = K[0][2], f = K[1][2];
+  const double A00 = fma(bb, c, -(f.x * f.x + f.y * f.y));
+  const double A11 = fma(a, c, -(ee.x * ee.x + ee.y * ee.y));
+  const double A22 = fma(a, bb, -(d.x * d.x + d.y * d.y));
+  const cplx A01 = csub(cmulc(f, ee), cscale(c, d));   // e conj(f) - c d
+  const cplx A02 = csub(cmul(d, f), cscale(bb, ee));   // d f - bb e
+  const cplx A12 = csub(cmulc(d, ee), cscale(a, f));   // conj(d) e - a f
+  const double det = fma(a, A00, fma(d.x, A01.x, fma(d.y, A01.y, fma(ee.x, A02.x, ee.y * A02.y))));
+  const double id = 1.0 / det;
+  x[0] = cscale(id, cadd(cscale(A00, b[0]), cadd(cmul(A01, b[1]), cmul(A02, b[2]))));
+  x[1] = cscale(id, cadd(cmulc(A01, b[0]), cadd(cscale(A11, b[1]), cmul(A12, b[2]))));
+  x[2] = cscale(id, cadd(cmulc(A02, b[0]), cadd(cmulc(A12, b[1]), cscale(A22, b[2]))));
 }
 
 // i-values per work-group of the solve pass: 1536 complex per LDS buffer gives
@@ -505,7 +515,11 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
       cplx bv[3], xv[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) bv[a] = f[(a * BI + di) * PT + r];
-      mode_solve(S, e1_s[di], Eb, e3[r], bv, xv);
+      cplx h[3], e[3];
+      mode_half_symbols(S, e1_s[di], Eb, e3[r], h);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) e[m] = mk(S.cf[m][0] + h[m].x, h[m].y);
+      symbol_solve(S, e, bv, xv);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         g[(a * BI + di) * PT + r] = xv[a];
@@ -533,8 +547,16 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
         c0[a] = cadd(v0, v1);
         c1[a] = csub(v0, v1);
       }
-      mode_solve(S, Ea, Eb, Eg, c0, z0);
-      mode_solve(S, mk(-Ea.x, -Ea.y), Eb, Eg, c1, z1);  // m1 = m1' + n1/2: alpha + pi
+      // m1 = m1' and m1 = m1' + n1/2 (alpha + pi: -Ea) share the half symbols
+      cplx h[3], ep[3], em[3];
+      mode_half_symbols(S, Ea, Eb, Eg, h);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        ep[m] = mk(S.cf[m][0] + h[m].x, h[m].y);
+        em[m] = mk(S.cf[m][0] - h[m].x, -h[m].y);
+      }
+      symbol_solve(S, ep, c0, z0);
+      symbol_solve(S, em, c1, z1);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         rz = fma(c0[a].x, z0[a].x, fma(c0[a].y, z0[a].y, rz));

@@ -351,10 +351,36 @@ __global__ void __launch_bounds__(tile_threads(TI, TJ))
     dkn[d - 1] = dk;
   }
   const bool inbox_pos = own && vi < iend && vj < jend;
+  // Whether this lane's tau at plane s is read by an output of the chunk: its
+  // own output node (plane s itself) or a forward step from an output node of
+  // the tile at plane s - e3 (e3 in {-1, 0, 1}).  The palette form takes the
+  // lane's part of that test, which does not depend on s, once here as one flag
+  // per e3; the dense form evaluates it per plane (position_needed), which
+  // measured faster there (its register allocation is at the limit).
+  bool need_m = false, need_0 = active && inbox_pos, need_p = false;  // e3 = -1, 0, +1
+  if constexpr (PAL) {
+    const int src_i = vi - 1;
+    const bool src_ok = active && src_i >= i0 && src_i < iend;
+#pragma unroll
+    for (int d = 1; d <= 4; ++d) {
+      int e2, e3;
+      fwd_offsets(g, src_i, d, e2, e3);
+      const int sj = vj - e2;
+      const bool hit = src_ok && sj >= j0 && sj < jend;
+      need_m = need_m || (hit && e3 < 0);
+      need_0 = need_0 || (hit && e3 == 0);
+      need_p = need_p || (hit && e3 > 0);
+    }
+  }
   auto needed_at = [&](int s) -> bool {
-    if (!active) return false;
-    if (inbox_pos && s >= k0 && s < k1) return true;
-    return position_needed(g, TI, TJ, i0, j0, iend, jend, k0, k1, ii, jj, s);
+    if constexpr (PAL) {
+      return (need_0 && s >= k0 && s < k1) || (need_p && s - 1 >= k0 && s - 1 < k1) ||
+             (need_m && s + 1 >= k0 && s + 1 < k1);
+    } else {
+      if (!active) return false;
+      if (inbox_pos && s >= k0 && s < k1) return true;
+      return position_needed(g, TI, TJ, i0, j0, iend, jend, k0, k1, ii, jj, s);
+    }
   };
   // stiffness (21 entries) and rho of a tau plane into one register set
   // (entry q of the node's run is q * PBR_CT_W doubles past entry 0)
