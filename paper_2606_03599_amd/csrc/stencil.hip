@@ -225,9 +225,13 @@ __host__ __device__ constexpr int tile_threads(int TI, int TJ) {
 constexpr int PART_G = 2;
 
 // Work-group layout: own lanes, then ring lanes, then idle lanes up to a wave.
+// Waves per SIMD a variant is compiled for: the palette form's 16 x 11 tile
+// (73 KB of LDS) lets two work-groups share a CU, so it gets half the registers.
+__host__ __device__ constexpr int stream_wpe(int TJ, bool PAL) { return PAL && TJ <= 11 ? 2 : 1; }
+
 template <int TI, int TJ, bool PAL>
 __global__ void __launch_bounds__(tile_threads(TI, TJ))
-    __attribute__((amdgpu_waves_per_eu(PAL ? 2 : 1, PAL ? 2 : 1)))
+    __attribute__((amdgpu_waves_per_eu(stream_wpe(TJ, PAL), stream_wpe(TJ, PAL))))
     apply_stream_kernel(ApplyArgs A) {
   constexpr int PI = TI + 1, PJ = TJ + 2, NP = PI * PJ;  // tau region
   constexpr int XI = TI + 2, XJ = TJ + 4, NX = XI * XJ;  // velocity region
@@ -611,8 +615,9 @@ _Pragma("unroll")                                                               
 
 constexpr int TILE_I = 16, TILE_J = 13;
 // Palette form: without the stiffness stream the kernel waits on LDS and
-// barriers rather than HBM, so it takes a tile whose LDS (73 KB plus the
-// palette) lets two work-groups share a CU.
+// barriers rather than HBM, so besides the 16 x 13 tile (one work-group per
+// CU) it has a 16 x 11 tile whose LDS (73 KB plus the palette) lets two
+// work-groups share a CU; the autotuner picks between them.
 constexpr int TILE_J_PAL = 11;
 constexpr int pal_lds_bytes(int npal) { return npal * 11 * 16; }
 // LDS of the palette form's static arrays (x ring, tau, reduction slots)
@@ -622,44 +627,63 @@ constexpr int PAL_STATIC_LDS = 4 * 3 * (TILE_I + 2) * (TILE_J_PAL + 4) * 16 +
 
 }  // namespace
 
-// Chunk length of a launch.  One work-group of the dense form fits a CU at a
-// time (two of the palette form when its palette is small), so a launch runs
-// in ceil(work-groups / resident work-groups) rounds, each as long
-// as its longest chunk plus its start-up (the two partial planes a chunk
-// computes at its ends and the first loads, which nothing overlaps); the model
-// cost rounds x (chunk + 4) ranks the chunk lengths that are whole groups of
-// PART_G planes (or the whole box).  The autotuner times the four best of
-// them with real launches the first time a (batch size, box, material form) is
-// seen outside stream capture, and keeps the fastest (a candidate replaces the
-// model's choice only if it is 5% faster) in the context; during capture, or
-// when timing fails, the model's best is used.  The launches are the caller's
-// own (same inputs, same outputs, rewritten), and since the (x, y) partials are
-// per tile and group no result depends on which chunk wins.
+// Work split of a launch: tile shape (16 x 13; for the palette form also
+// 16 x 11) and chunk length.  A tile shape fits one work-group per CU (two for
+// the palette form's 16 x 11 tile when its palette is small), so a launch runs
+// in ceil(work-groups / resident work-groups) rounds, each as long as its
+// longest chunk plus its start-up (the two partial planes a chunk computes at
+// its ends and the first loads, which nothing overlaps); per tile shape the
+// model cost rounds x (chunk + 4) ranks the chunk lengths that are whole groups
+// of PART_G planes (or the whole box).  The autotuner times the four best
+// candidates (the two best of each shape when there are two) with real
+// launches the first time a (batch size, box, material form) is seen outside
+// stream capture, and keeps the fastest in the context; a candidate replaces
+// the first shape's model choice only if it is 5% faster, since candidates
+// often time within noise of each other and a stable choice keeps the launch
+// (and its partials) the same from run to run.  During capture, or when timing
+// fails, the model's choice is used.  The launches are the caller's own (same
+// inputs, same outputs, rewritten).  The (x, y) partials are per tile and group
+// of planes, so no result depends on the chunk; the tile shape changes how
+// they are grouped, so inner products may round differently between shapes.
 template <class F>
-int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, int pal, int per_cu, long tiles, F&& launch,
-                int* out) {
+int tuned_split(pbr_ctx* c, const Geo& g, int nb, int pal, F&& launch, int* tj_out, int* out) {
   for (const auto& e : c->stencil_tune)
     if (e.nb == nb && e.L1 == g.L1 && e.L2 == g.L2 && e.L3 == g.L3 && e.pal == pal &&
         e.chunk > 0) {
+      *tj_out = e.tj;
       *out = e.chunk;
       return ST_OK;
     }
-  const int cus = std::max(1, c->cus) * per_cu;  // work-groups resident at once
-  std::vector<std::pair<long, int>> cand;  // (model cost, chunk)
-  for (int ch = std::min(PART_G, g.L3); ch <= g.L3; ++ch) {
-    if (ch % PART_G != 0 && ch != g.L3) continue;
-    const long wgs = (long)nb * tiles * ((g.L3 + ch - 1) / ch);
-    cand.push_back({((wgs + cus - 1) / cus) * (ch + 4), ch});
+  const int shapes[2] = {pal ? TILE_J_PAL : TILE_J, TILE_J};
+  const int nshapes = pal ? 2 : 1;
+  std::vector<std::pair<int, int>> pick;  // (tile height, chunk) in timing order
+  for (int sh = 0; sh < nshapes; ++sh) {
+    const int tj = shapes[sh];
+    const int per_cu =
+        tj == TILE_J_PAL && 2 * (PAL_STATIC_LDS + 256 + pal_lds_bytes(c->npal)) <= 160 * 1024
+            ? 2
+            : 1;
+    const int slots = std::max(1, c->cus) * per_cu;  // work-groups resident at once
+    const long tiles = (long)((g.L1 + TILE_I - 1) / TILE_I) * ((g.L2 + tj - 1) / tj);
+    std::vector<std::pair<long, int>> cand;  // (model cost, chunk)
+    for (int ch = std::min(PART_G, g.L3); ch <= g.L3; ++ch) {
+      if (ch % PART_G != 0 && ch != g.L3) continue;
+      const long wgs = (long)nb * tiles * ((g.L3 + ch - 1) / ch);
+      cand.push_back({((wgs + slots - 1) / slots) * (ch + 4), ch});
+    }
+    std::stable_sort(cand.begin(), cand.end(),
+                     [](const std::pair<long, int>& a, const std::pair<long, int>& b) {
+                       return a.first < b.first;
+                     });
+    const size_t keep = std::min<size_t>(nshapes == 1 ? 4 : 2, cand.size());
+    for (size_t k = 0; k < keep; ++k) pick.push_back({tj, cand[k].second});
   }
-  std::stable_sort(cand.begin(), cand.end(),
-                   [](const std::pair<long, int>& a, const std::pair<long, int>& b) {
-                     return a.first < b.first;
-                   });
-  *out = cand[0].second;
+  *tj_out = pick[0].first;
+  *out = pick[0].second;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(c->stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
     return ST_OK;
-  const int ncand = (int)std::min<size_t>(4, cand.size());
+  const int ncand = (int)pick.size();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ncand > 1 && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
     float best_ms = -1.0f;
@@ -667,20 +691,21 @@ int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, int pal, int per_cu, long tile
     for (int r = 0; r < 2 && ok; ++r)  // the first round also warms the caches
       for (int k = 0; k < ncand && ok; ++k) {
         ok = hipEventRecord(e0, c->stream) == hipSuccess;
-        if (ok) PBR_TRY(launch(cand[k].second));
+        if (ok) PBR_TRY(launch(pick[k].first, pick[k].second));
         ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
              hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.0f;
         ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-        // another candidate must beat the model's choice clearly: candidates of
-        // equal model cost often time within noise of each other, and a stable
-        // choice keeps the launch (and its partials) the same from run to run
         if (ok && r == 1 && (best_ms < 0.0f || ms < 0.95f * best_ms)) {
           best_ms = ms;
-          *out = cand[k].second;
+          *tj_out = pick[k].first;
+          *out = pick[k].second;
         }
       }
-    if (!ok) *out = cand[0].second;
+    if (!ok) {
+      *tj_out = pick[0].first;
+      *out = pick[0].second;
+    }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -691,6 +716,7 @@ int tuned_chunk(pbr_ctx* c, const Geo& g, int nb, int pal, int per_cu, long tile
   slot.L2 = g.L2;
   slot.L3 = g.L3;
   slot.pal = pal;
+  slot.tj = *tj_out;
   slot.chunk = *out;
   return ST_OK;
 }
@@ -736,11 +762,8 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
   A.npal = c->npal;
   A.s = s;
   A.tiles_i = (g.L1 + TILE_I - 1) / TILE_I;
-  const int tj = pal ? TILE_J_PAL : TILE_J;
-  A.tiles_j = (g.L2 + tj - 1) / tj;
-  const long tiles = (long)A.tiles_i * A.tiles_j;
-  const long np = tiles * ((g.L3 + PART_G - 1) / PART_G);  // (x, y) partials per layout
-  if (nparts) *nparts = (int)np;
+  // (x, y) partials per layout: the most any tile shape needs
+  const long np_max = apply_partials(c, g.blocked ? 0 : -1);
   // layouts ordered by material (stable), grouped by equal material
   int ord[PBR_MAX_BATCH];
   for (int t = 0; t < nb; ++t) ord[t] = t;
@@ -762,30 +785,35 @@ int launch_apply_batch(pbr_ctx* c, const Geo& g, int nb, const ApplyLayout* L, d
     B.a = L[t].block >= 0 ? L[t].block >> 1 : 0;
     B.c = L[t].block >= 0 ? L[t].block & 1 : 0;
     for (int l = 0; l < 3; ++l) B.ph[l] = L[t].ph[l];
-    if (B.part && np > part_cap) {
+    if (B.part && np_max > part_cap) {
       c->set_error("grid too large for the PCG partial buffers");
       return ST_EINVAL;
     }
   }
-  auto launch = [&](int chunk) -> int {
+  auto launch = [&](int tj, int chunk) -> int {
+    A.tiles_j = (g.L2 + tj - 1) / tj;
     A.chunk = chunk;
-    A.per = (int)(tiles * ((g.L3 + chunk - 1) / chunk));
+    A.per = (int)((long)A.tiles_i * A.tiles_j * ((g.L3 + chunk - 1) / chunk));
     const unsigned grid = (unsigned)((long)A.per * nb);
-    if (pal)
+    if (pal && tj == TILE_J_PAL)
       hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J_PAL, true>), dim3(grid),
                          dim3(tile_threads(TILE_I, TILE_J_PAL)), pal_lds_bytes(c->npal),
                          c->stream, A);
+    else if (pal)
+      hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J, true>), dim3(grid),
+                         dim3(tile_threads(TILE_I, TILE_J)), pal_lds_bytes(c->npal), c->stream,
+                         A);
     else
       hipLaunchKernelGGL((apply_stream_kernel<TILE_I, TILE_J, false>), dim3(grid),
                          dim3(tile_threads(TILE_I, TILE_J)), 0, c->stream, A);
     PBR_HIP(c, hipGetLastError());
     return ST_OK;
   };
-  int chunk = 0;
-  const int per_cu =
-      pal && 2 * (PAL_STATIC_LDS + 256 + pal_lds_bytes(c->npal)) <= 160 * 1024 ? 2 : 1;
-  PBR_TRY(tuned_chunk(c, g, nb, pal, per_cu, tiles, launch, &chunk));
-  return launch(chunk);
+  int tj = 0, chunk = 0;
+  PBR_TRY(tuned_split(c, g, nb, pal, launch, &tj, &chunk));
+  if (nparts)
+    *nparts = (int)((long)A.tiles_i * ((g.L2 + tj - 1) / tj) * ((g.L3 + PART_G - 1) / PART_G));
+  return launch(tj, chunk);
 }
 
 int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, cplx* y,
