@@ -152,6 +152,17 @@ pbr_status pbr_set_material(pbr_ctx *c, const double *C21, const double *rho,
 pbr_status pbr_set_palette(pbr_ctx *c, int enable);
 int pbr_material_palette(const pbr_ctx *c);
 
+/* Tile shape of the operator kernel (the fused matvec of Sec. 6.1 in pbr_apply,
+ * pbr_apply_blocks and the solvers): ti x tj nodes of the (i, j) plane per
+ * work-group.  ti = tj = 0 (the default) lets the autotuner choose per batch
+ * size, box and material form, timing candidate shapes and chunk lengths on the
+ * first launch; 16 x 13 (both forms) or 16 x 11 (palette form) pins that shape,
+ * with only the chunk length tuned.  A pinned shape the current form does not
+ * have is ignored for that form.  Operator outputs do not depend on the shape;
+ * inner products of the fused PCG are summed per tile and may round
+ * differently.  PBR_EINVAL for a NULL context or any other shape. */
+pbr_status pbr_set_stencil_shape(pbr_ctx *c, int ti, int tj);
+
 /* Override the constant reference material of the preconditioner
  * (K(m) = Bhat(m) C_ref Bhat(m)^H + shift * rho_ref * I_3, Sec. 5.3-5.4): C21_ref
  * is 21 host doubles in the C21 order, rho_ref > 0. */

@@ -337,6 +337,21 @@ pbr_status pbr_set_palette(pbr_ctx* c, int enable) {
   return PBR_OK;
 }
 
+pbr_status pbr_set_stencil_shape(pbr_ctx* c, int ti, int tj) {
+  if (!c) return PBR_EINVAL;
+  const bool ok = (ti == 0 && tj == 0) || (ti == 16 && (tj == 13 || tj == 11));
+  if (!ok) {
+    c->set_error("stencil shape must be 0 x 0 (autotuned), 16 x 13 or 16 x 11");
+    return PBR_EINVAL;
+  }
+  if (c->pin_ti != ti || c->pin_tj != tj) {
+    c->pin_ti = ti;
+    c->pin_tj = tj;
+    ++c->mat_gen;  // captured PCG graphs hold the old launch shape
+  }
+  return PBR_OK;
+}
+
 int pbr_material_palette(const pbr_ctx* c) {
   if (!c || !c->have_material) return -1;
   return c->use_palette ? c->npal : 0;

@@ -89,9 +89,11 @@ struct pbr_ctx {
   int cus = 256;       // compute units of the device
   // stencil chunk lengths chosen by the autotuner, per (batch size, box)
   struct StencilTune {
-    int nb = 0, L1 = 0, L2 = 0, L3 = 0, pal = 0, tj = 0, chunk = 0;
+    int nb = 0, L1 = 0, L2 = 0, L3 = 0, pal = 0, pin_ti = 0, pin_tj = 0;
+    int ti = 0, tj = 0, chunk = 0;
   } stencil_tune[PBR_TUNE_SLOTS];
   int stencil_tune_next = 0;
+  int pin_ti = 0, pin_tj = 0;  // stencil tile shape pinned by pbr_set_stencil_shape (0: tuned)
   hipStream_t stream = nullptr;
   bool own_stream = false;
 

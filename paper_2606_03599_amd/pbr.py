@@ -69,6 +69,7 @@ _SIGS = {
     "pbr_set_reference": (ctypes.c_int, [_vp, _dp, ctypes.c_double]),
     "pbr_set_palette": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pbr_material_palette": (ctypes.c_int, [_vp]),
+    "pbr_set_stencil_shape": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pbr_default_shift": (ctypes.c_double, [_vp]),
     "pbr_block_dim": (ctypes.c_long, [_vp, ctypes.c_int]),
     "pbr_block_gather": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]),
@@ -209,6 +210,10 @@ def pbr_set_palette(ctx, enable):
 
 def pbr_material_palette(ctx):
     return lib().pbr_material_palette(ctx)
+
+
+def pbr_set_stencil_shape(ctx, ti, tj):
+    _check(ctx, lib().pbr_set_stencil_shape(ctx, int(ti), int(tj)))
 
 
 def pbr_block_dim(ctx, block):
@@ -417,6 +422,11 @@ class Context:
     def palette_size(self):
         """Palette rows the kernels read; 0 for the dense form."""
         return pbr_material_palette(self.h)
+
+    def set_stencil_shape(self, ti=0, tj=0):
+        """Pin the operator kernel's tile shape (16 x 13, or 16 x 11 for the palette
+        form); 0, 0 returns the choice to the autotuner."""
+        pbr_set_stencil_shape(self.h, ti, tj)
 
     def block_dim(self, block):
         return pbr_block_dim(self.h, block)

@@ -85,6 +85,48 @@ def test_palette_matches_dense_and_oracle(dims, K, A_lat):
     ctx.close()
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 8), (12, 10, 14), (34, 30, 6)])
+def test_every_stencil_shape_gives_the_same_operator(dims):
+    """Each tile shape, pinned (16 x 13 in both forms, 16 x 11 in the palette
+    form; 16 x 11 pinned on the dense form falls back to its own shape), gives the
+    same output bit for bit, full space, single blocks and the four-block launch,
+    and matches the oracle; grids with ragged tiles in i and j."""
+    log(f"stencil shapes dims={dims}")
+    n = int(np.prod(dims))
+    C21, rho = labelled_field(dims, 5, seed=n)
+    ctx = make_ctx(dims, C21, rho)
+    kap, s = (0.15, -0.05, 0.3), 0.8
+    x = complex_gaussian(3 * n, seed=4)
+    xs = [Bk.gather(x, dims, b) for b in range(4)]
+    x4 = to_dev(np.concatenate(xs))
+    A = D.assemble_A(dims, kap, C21) if n <= 2000 else None
+    outs = []
+    for enable, shape in ((True, (16, 11)), (True, (16, 13)), (False, (16, 13)),
+                          (False, (16, 11)), (True, (0, 0))):
+        ctx.set_palette(enable)
+        ctx.set_stencil_shape(*shape)
+        y = to_host(ctx.apply(kap, -1, s, to_dev(x), to_dev(np.zeros_like(x))))
+        yb = [to_host(ctx.apply(kap, b, s, to_dev(xs[b]), to_dev(np.zeros_like(xs[b]))))
+              for b in range(4)]
+        y4 = to_host(ctx.apply_blocks(kap, s, x4, to_dev(np.zeros(3 * n, complex))))
+        outs.append((y, yb, y4))
+    for y, yb, y4 in outs[1:]:
+        assert np.array_equal(y, outs[0][0])
+        assert np.array_equal(y4, outs[0][2])
+        for b in range(4):
+            assert np.array_equal(yb[b], outs[0][1][b])
+    if A is not None:
+        M = D.assemble_M(rho)
+        assert rel(outs[0][0], A @ x + s * (M @ x)) <= TOL
+    nb3 = 3 * n // 4
+    for b in range(4):
+        assert np.array_equal(outs[0][2][b * nb3:(b + 1) * nb3], outs[0][1][b])
+        assert rel(outs[0][1][b], Bk.gather(outs[0][0], dims, b)) <= TOL
+    with pytest.raises(pbr.PbrError):
+        ctx.set_stencil_shape(8, 22)
+    ctx.close()
+
+
 def test_palette_size_rules():
     dims = (8, 8, 8)
     ctx = pbr.Context(dims)
