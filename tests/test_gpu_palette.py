@@ -85,15 +85,17 @@ def test_palette_matches_dense_and_oracle(dims, K, A_lat):
     ctx.close()
 
 
-@pytest.mark.parametrize("dims", [(8, 8, 8), (12, 10, 14), (34, 30, 6)])
-def test_every_stencil_shape_gives_the_same_operator(dims):
+@pytest.mark.parametrize("dims,K", [((8, 8, 8), 5), ((8, 8, 8), 256), ((12, 10, 14), 5),
+                                    ((34, 30, 6), 5)])
+def test_every_stencil_shape_gives_the_same_operator(dims, K):
     """Each tile shape, pinned (16 x 13 in both forms, 16 x 11 in the palette
     form; 16 x 11 pinned on the dense form falls back to its own shape), gives the
     same output bit for bit, full space, single blocks and the four-block launch,
-    and matches the oracle; grids with ragged tiles in i and j."""
-    log(f"stencil shapes dims={dims}")
+    and matches the oracle; grids with ragged tiles in i and j, and a 256-row
+    palette (45 KB of LDS on top of the tile's)."""
+    log(f"stencil shapes dims={dims} K={K}")
     n = int(np.prod(dims))
-    C21, rho = labelled_field(dims, 5, seed=n)
+    C21, rho = labelled_field(dims, K, seed=n + K)
     ctx = make_ctx(dims, C21, rho)
     kap, s = (0.15, -0.05, 0.3), 0.8
     x = complex_gaussian(3 * n, seed=4)
