@@ -1,6 +1,7 @@
 /*
- * pbr_host.h -- host-side building blocks of libpbr's outer eigensolver, exported
- * so they can be used and checked without a GPU.
+ * pbr_host.h -- host-side building blocks of libpbr (the outer eigensolver's
+ * dense steps and the material's palette form), exported so they can be used
+ * and checked without a GPU.
  */
 #ifndef PBR_HOST_H
 #define PBR_HOST_H
@@ -28,6 +29,17 @@ int pbr_host_heev(int m, const double *A, double *w, double *V);
  * arguments or when the union holds fewer than nev values. */
 int pbr_host_merge(int nev, const int nev_b[4], const double *const vals[4],
                    double *merged);
+
+/* Palette form of the nodewise material (Eq. 3.15; the form the operator
+ * kernels read when it exists, see pbr_set_material): the distinct rows
+ * (C21[x][0..20], rho[x]) of the n nodes, compared bit for bit and numbered in
+ * order of first appearance, written to rows (22 doubles each, capacity 256
+ * rows), and each node's row number to idx[x].  C21 (n x 21), rho (n) in the
+ * layout of pbr_set_material; all pointers host memory owned by the caller.
+ * Returns the number of rows (1..256), 0 when the material has more than 256
+ * distinct rows (rows and idx then hold partial results), -1 on bad arguments. */
+int pbr_host_palette(long n, const double *C21, const double *rho, double *rows,
+                     unsigned char *idx);
 
 #ifdef __cplusplus
 }

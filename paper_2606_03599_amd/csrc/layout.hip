@@ -6,6 +6,7 @@
 #include <cstring>
 #include <vector>
 
+#include "../../include/pbr_host.h"
 #include "context.hpp"
 
 namespace {
@@ -111,55 +112,6 @@ int alloc_material(pbr_ctx* c, DevMaterial& M, long N, long ct_len) {
   return ST_OK;
 }
 
-// Distinct (C21, rho) rows of the material, compared bit for bit, in order of
-// first appearance, and each node's row (natural order).  Returns false as soon
-// as a (PBR_PAL_MAX + 1)-th row appears.  Runs of equal rows are checked
-// against the previous node first; other rows go through a small open-address
-// hash table.
-bool build_palette(long n, const double* C21, const double* rho, std::vector<double>& pal,
-                   std::vector<unsigned char>& idx) {
-  constexpr int HS = 4 * PBR_PAL_MAX;  // power of two
-  int slot_row[HS];
-  for (int& v : slot_row) v = -1;
-  pal.clear();
-  idx.assign((size_t)n, 0);
-  double row[22];
-  int last = -1;
-  for (long x = 0; x < n; ++x) {
-    std::memcpy(row, C21 + (size_t)x * 21, 21 * sizeof(double));
-    row[21] = rho[x];
-    if (last >= 0 && std::memcmp(row, &pal[(size_t)last * 22], sizeof(row)) == 0) {
-      idx[x] = (unsigned char)last;
-      continue;
-    }
-    unsigned long long h = 0x9e3779b97f4a7c15ULL;
-    for (int q = 0; q < 22; ++q) {
-      unsigned long long b;
-      std::memcpy(&b, &row[q], 8);
-      h = (h ^ b) * 0xff51afd7ed558ccdULL;
-      h ^= h >> 29;
-    }
-    int sl = (int)(h & (HS - 1));
-    int found = -1;
-    while (slot_row[sl] >= 0) {
-      if (std::memcmp(row, &pal[(size_t)slot_row[sl] * 22], sizeof(row)) == 0) {
-        found = slot_row[sl];
-        break;
-      }
-      sl = (sl + 1) & (HS - 1);
-    }
-    if (found < 0) {
-      const int np = (int)(pal.size() / 22);
-      if (np == PBR_PAL_MAX) return false;
-      pal.insert(pal.end(), row, row + 22);
-      slot_row[sl] = np;
-      found = np;
-    }
-    idx[x] = (unsigned char)found;
-    last = found;
-  }
-  return true;
-}
 
 // Tiles of one layout from its stiffness planes and rho.
 void launch_tile(pbr_ctx* c, int L1, int L2, int L3, const double* C, DevMaterial& M) {
@@ -201,9 +153,10 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
   // natural planes (and one block's planes) live only during the upload
   double* tmp = nullptr;
   double* tmpb = nullptr;
-  std::vector<double> hpal;
-  std::vector<unsigned char> hidx;
-  const bool fits = build_palette(n, C21, rho, hpal, hidx);
+  std::vector<double> hpal((size_t)PBR_PAL_MAX * 22);
+  std::vector<unsigned char> hidx((size_t)n);
+  const int nrows = pbr_host_palette(n, C21, rho, hpal.data(), hidx.data());
+  const bool fits = nrows > 0;
   c->npal = 0;
   int st = dev_alloc(c, (void**)&tmp, sizeof(double) * 21 * n);
   if (st == ST_OK && c->even) st = dev_alloc(c, (void**)&tmpb, sizeof(double) * 21 * (n / 4));
@@ -217,7 +170,7 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
     launch_tile(c, c->n1, c->n2, c->n3, tmp, F);
     PBR_HIP(c, hipGetLastError());
     if (fits) {
-      PBR_HIP(c, hipMemcpyAsync(c->pal, hpal.data(), sizeof(double) * hpal.size(),
+      PBR_HIP(c, hipMemcpyAsync(c->pal, hpal.data(), sizeof(double) * 22 * nrows,
                                 hipMemcpyHostToDevice, c->stream));
       PBR_HIP(c, hipMemcpyAsync(F.idx, hidx.data(), (size_t)n, hipMemcpyHostToDevice, c->stream));
     }
@@ -249,7 +202,7 @@ int upload_material(pbr_ctx* c, const double* C21, const double* rho) {
   dev_free(tmpb);
   if (st != ST_OK) return st;
   PBR_HIP(c, e);
-  c->npal = fits ? (int)(hpal.size() / 22) : 0;
+  c->npal = fits ? nrows : 0;
   return ST_OK;
 }
 

@@ -101,6 +101,8 @@ _SIGS = {
     "pbr_last_error": (ctypes.c_char_p, [_vp]),
     "pbr_destroy": (None, [_vp]),
     "pbr_host_heev": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp]),
+    "pbr_host_palette": (ctypes.c_int, [ctypes.c_long, _dp, _dp, _dp,
+                                        ctypes.POINTER(ctypes.c_ubyte)]),
     "pbr_host_merge": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(_dp), _dp]),
 }
@@ -372,6 +374,24 @@ def pbr_host_merge(nev, block_vals):
     out = np.zeros(int(nev))
     mask = lib().pbr_host_merge(int(nev), nb, ptrs, out.ctypes.data_as(_dp))
     return mask, out
+
+
+def pbr_host_palette(C21, rho):
+    """(rows (k x 22), idx (n,) uint8) of the material's palette form, or None
+    when it has more than 256 distinct rows."""
+    C = np.ascontiguousarray(np.asarray(C21, dtype=np.float64))
+    r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
+    n = r.size
+    if C.shape != (n, 21):
+        raise ValueError("C21 must be n x 21 and rho n")
+    rows = np.zeros((256, 22))
+    idx = np.zeros(n, dtype=np.uint8)
+    k = lib().pbr_host_palette(n, C.ctypes.data_as(_dp), r.ctypes.data_as(_dp),
+                               rows.ctypes.data_as(_dp),
+                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    if k < 0:
+        raise PbrError(k, "pbr_host_palette failed")
+    return None if k == 0 else (rows[:k].copy(), idx)
 
 
 def band_paths(contexts, kappas_list, nev, blocked=True, shift=0.0, opts=None):
