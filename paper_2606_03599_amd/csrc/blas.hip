@@ -4,6 +4,7 @@
 // fixed tree order (wave shuffles + LDS) and writes one partial; a single
 // work-group then sums the partials in index order.  Repeated runs are
 // therefore bit-identical.
+#include <algorithm>
 #include <cmath>
 
 #include "blas.hpp"
@@ -216,37 +217,72 @@ __global__ void gemv_sub_kernel(long n, int m, const cplx* __restrict__ U, long 
   }
 }
 
-// part[wg*m + j] (complex, 2 doubles each) = slice sum of conj(U_j) w
+// part[wg*m + j] (complex, 2 doubles each) = slice sum of conj(U_j) w.  Four
+// columns per sweep of the slice (w read once per sweep, four column loads in
+// flight), their eight sums reduced together: one barrier per four columns.
+constexpr int MD_COLS = 4;
 __global__ void __launch_bounds__(RT) multi_dot_kernel(long n, int m, const cplx* __restrict__ U,
                                                        long ld, const cplx* __restrict__ w,
                                                        double* __restrict__ part) {
-  __shared__ double sh[RT / 64];
-  for (int j = 0; j < m; ++j) {
-    double re = 0.0, im = 0.0;
+  __shared__ double sh[2 * MD_COLS][RT / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < m; j0 += MD_COLS) {
+    const int nc = min(MD_COLS, m - j0);
+    double re[MD_COLS], im[MD_COLS];
+#pragma unroll
+    for (int c = 0; c < MD_COLS; ++c) re[c] = im[c] = 0.0;
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (long)gridDim.x * blockDim.x) {
-      const cplx u = U[(long)j * ld + t], x = w[t];
-      re = fma(u.x, x.x, fma(u.y, x.y, re));
-      im = fma(u.x, x.y, fma(-u.y, x.x, im));
+      const cplx x = w[t];
+#pragma unroll
+      for (int c = 0; c < MD_COLS; ++c) {
+        if (c < nc) {
+          const cplx u = U[(long)(j0 + c) * ld + t];
+          re[c] = fma(u.x, x.x, fma(u.y, x.y, re[c]));
+          im[c] = fma(u.x, x.y, fma(-u.y, x.x, im[c]));
+        }
+      }
     }
-    const double sr = block_sum(re, sh);
-    const double si = block_sum(im, sh);
-    if (threadIdx.x == 0) {
-      part[((long)blockIdx.x * m + j) * 2] = sr;
-      part[((long)blockIdx.x * m + j) * 2 + 1] = si;
+#pragma unroll
+    for (int c = 0; c < MD_COLS; ++c) {
+      const double a = wave_sum(re[c]), b = wave_sum(im[c]);
+      if (lane == 0) {
+        sh[2 * c][wid] = a;
+        sh[2 * c + 1][wid] = b;
+      }
     }
+    __syncthreads();
+    if (threadIdx.x < 2 * nc) {
+      double r = 0.0;
+      for (int v = 0; v < (int)(blockDim.x >> 6); ++v) r += sh[threadIdx.x][v];
+      part[((long)blockIdx.x * m + j0) * 2 + threadIdx.x] = r;
+    }
+    __syncthreads();
   }
 }
 
-// V[:, 0:k] = U[:, 0:m] Y[0:m, 0:k]  (Y column-major m x k, complex, device)
+// V[:, 0:k] = U[:, 0:m] Y[0:m, 0:k]  (Y column-major m x k, complex, device).
+// Eight output columns per sweep over j, so each U entry is loaded k/8 times
+// rather than k times; every output sums over j in ascending order.
+constexpr int CB_COLS = 8;
 __global__ void combine_kernel(long n, int m, int k, const cplx* __restrict__ U, long ld,
                                const cplx* __restrict__ Y, cplx* __restrict__ V, long ldv) {
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long)gridDim.x * blockDim.x) {
-    for (int c = 0; c < k; ++c) {
-      cplx acc = mk(0, 0);
-      for (int j = 0; j < m; ++j) acc = cmad(U[(long)j * ld + t], Y[(long)c * m + j], acc);
-      V[(long)c * ldv + t] = acc;
+    for (int c0 = 0; c0 < k; c0 += CB_COLS) {
+      const int nc = min(CB_COLS, k - c0);
+      cplx acc[CB_COLS];
+#pragma unroll
+      for (int cc = 0; cc < CB_COLS; ++cc) acc[cc] = mk(0, 0);
+      for (int j = 0; j < m; ++j) {
+        const cplx u = U[(long)j * ld + t];
+#pragma unroll
+        for (int cc = 0; cc < CB_COLS; ++cc)
+          if (cc < nc) acc[cc] = cmad(u, Y[(long)(c0 + cc) * m + j], acc[cc]);
+      }
+#pragma unroll
+      for (int cc = 0; cc < CB_COLS; ++cc)
+        if (cc < nc) V[(long)(c0 + cc) * ldv + t] = acc[cc];
     }
   }
 }
@@ -381,7 +417,9 @@ int dot_cplx_async(pbr_ctx* c, hipStream_t st_, long n, const cplx* a, const cpl
 
 int multi_dot_async(pbr_ctx* c, hipStream_t st_, long n, int m, const cplx* U, long ld, const cplx* w, double* part,
                     double* out) {
-  const unsigned g = grid_for(n) > 256 ? 256 : grid_for(n);
+  // partials: g rows of 2m doubles in a buffer of 1024 x 256
+  const unsigned gmax = (unsigned)std::max(1, 1024 * 128 / std::max(1, m));
+  const unsigned g = std::min(grid_for(n), gmax);
   LAUNCH(multi_dot_kernel, g, n, m, U, ld, w, part);
   LAUNCH(reduce_cols_kernel, 1, (int)g, 2 * m, 2 * m, (const double*)part, out);
   return ST_OK;
