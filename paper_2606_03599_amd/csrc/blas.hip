@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(RT) reduce_cols_kernel(int np, int width, int 
                                                          const double* __restrict__ part,
                                                          double* __restrict__ out) {
   __shared__ double sh[RT / 64];
-  for (int j = 0; j < width; ++j) {
+  for (int j = blockIdx.x; j < width; j += gridDim.x) {  // one column per work-group
     double acc = 0.0;
     for (int p = threadIdx.x; p < np; p += blockDim.x) acc += part[(long)p * stride + j];
     const double s = block_sum(acc, sh);
@@ -421,7 +421,7 @@ int multi_dot_async(pbr_ctx* c, hipStream_t st_, long n, int m, const cplx* U, l
   const unsigned gmax = (unsigned)std::max(1, 1024 * 128 / std::max(1, m));
   const unsigned g = std::min(grid_for(n), gmax);
   LAUNCH(multi_dot_kernel, g, n, m, U, ld, w, part);
-  LAUNCH(reduce_cols_kernel, 1, (int)g, 2 * m, 2 * m, (const double*)part, out);
+  LAUNCH(reduce_cols_kernel, 2 * m, (int)g, 2 * m, 2 * m, (const double*)part, out);
   return ST_OK;
 }
 
@@ -439,7 +439,7 @@ int combine(pbr_ctx* c, hipStream_t st_, long n, int m, int k, const cplx* U, lo
 int proj_gamma(pbr_ctx* c, hipStream_t st_, long N, int nf, const double* W, cplx* v, double* part, double* coef) {
   const unsigned g = grid_for(N) > 256 ? 256 : grid_for(N);
   LAUNCH(proj_dot_kernel, g, N, nf, W, (const cplx*)v, part);
-  LAUNCH(reduce_cols_kernel, 1, (int)g, nf * 6, nf * 6, (const double*)part, coef);
+  LAUNCH(reduce_cols_kernel, nf * 6, (int)g, nf * 6, nf * 6, (const double*)part, coef);
   LAUNCH(proj_sub_kernel, grid_for(N), N, nf, W, (const double*)coef, v);
   return ST_OK;
 }
