@@ -106,6 +106,7 @@ struct pbr_ctx {
   int npal = 0;              // palette rows (0: the material has more than PBR_PAL_MAX)
   double* pal = nullptr;     // PBR_PAL_MAX x 22 doubles on the device
   bool use_palette = true;   // pbr_set_palette
+  int pcg_hint = 0;          // PCG iterations of the last fused solve (first host check)
   // Bumped whenever the material, the reference material or the stiffness
   // form changes: launch arguments captured in a graph depend on all three.
   unsigned long mat_gen = 0;

@@ -391,16 +391,28 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const LayoutRef* L, double shift,
       int npq = 0;
       PBR_TRY(launch_apply_batch(c, g, nb, AL, shift, P[0].part_cap, &npq));
     }
+    // The first host check comes after about as many iterations as the previous
+    // solve of this context needed (solves along a path need nearly the same
+    // number); iterations past convergence are no-ops on the device (every pass
+    // returns once the layout's flag is set), so only the host waits change.
     int done_iters = 0;
+    bool first = true;
     for (;;) {
       const int todo = std::min(chunk, o.maxit_inner - done_iters);
       if (todo <= 0) break;
+      int burst = 1;
+      if (first && todo == chunk)
+        burst = std::max(1, std::min((c->pcg_hint - 2 * chunk) / chunk,
+                                     (o.maxit_inner - done_iters) / chunk));
+      first = false;
       if (o.graphs && todo == chunk && !c->graphs_broken)
         PBR_TRY(ensure_pcg_graph(c, nb, L, b, x, shift, chunk, iterate));
-      if (o.graphs && todo == chunk && !c->graphs_broken)
-        PBR_HIP(c, hipGraphLaunch(c->pcg_graph.exec, c->stream));
-      else
-        PBR_TRY(iterate(todo));
+      for (int rep = 0; rep < burst; ++rep) {
+        if (o.graphs && todo == chunk && !c->graphs_broken)
+          PBR_HIP(c, hipGraphLaunch(c->pcg_graph.exec, c->stream));
+        else
+          PBR_TRY(iterate(todo));
+      }
       PBR_TRY(read_states(c, hs));
       bool all = true;
       done_iters = 0;
@@ -411,6 +423,7 @@ int pcg_solve_batch(pbr_ctx* c, int nb, const LayoutRef* L, double shift,
       }
       if (all) break;
     }
+    c->pcg_hint = done_iters;
     // the x update of an iteration that ended at the convergence test
     PcgScalars* sts[PBR_MAX_BATCH];
     const cplx* ps[PBR_MAX_BATCH];
