@@ -79,7 +79,10 @@ typedef struct pbr_opts {
   int maxit_inner;   /* maximum PCG iterations per solve */
   int ncv;           /* Krylov basis size; 0 = automatic (2*nev + 10, at most dim) */
   int precond;       /* 1 = FFT-diagonal preconditioner, 0 = none */
-  int check_every;   /* PCG iterations between host convergence checks; 0 = automatic */
+  int check_every;   /* PCG iterations between host convergence checks; 0 = automatic
+                        (10).  The fused PCG of the blocked solvers makes its first
+                        check after about as many iterations as the context's previous
+                        solve took; iterations past convergence change nothing. */
   int seed;          /* seed of the (deterministic) start vector */
   int concurrent;    /* pbr_eigs_merged / pbr_band_path: 1 = independent solves (the
                         four blocks, and up to 4 wave vectors of a path) advance in
