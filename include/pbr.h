@@ -80,7 +80,7 @@ typedef struct pbr_opts {
   int ncv;           /* Krylov basis size; 0 = automatic (2*nev + 10, at most dim) */
   int precond;       /* 1 = FFT-diagonal preconditioner, 0 = none */
   int check_every;   /* PCG iterations between host convergence checks; 0 = automatic
-                        (10).  The fused PCG of the blocked solvers makes its first
+                        (10).  The fused PCG (precond = 1) makes its first
                         check after about as many iterations as the context's previous
                         solve took; iterations past convergence change nothing. */
   int seed;          /* seed of the (deterministic) start vector */
