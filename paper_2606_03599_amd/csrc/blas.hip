@@ -439,7 +439,8 @@ int combine(pbr_ctx* c, hipStream_t st_, long n, int m, int k, const cplx* U, lo
 int proj_gamma(pbr_ctx* c, hipStream_t st_, long N, int nf, const double* W, cplx* v, double* part, double* coef) {
   const unsigned g = grid_for(N) > 256 ? 256 : grid_for(N);
   LAUNCH(proj_dot_kernel, g, N, nf, W, (const cplx*)v, part);
-  LAUNCH(reduce_cols_kernel, nf * 6, (int)g, nf * 6, nf * 6, (const double*)part, coef);
+  LAUNCH(reduce_cols_kernel, std::max(1, nf * 6), (int)g, nf * 6, nf * 6, (const double*)part,
+         coef);
   LAUNCH(proj_sub_kernel, grid_for(N), N, nf, W, (const double*)coef, v);
   return ST_OK;
 }
