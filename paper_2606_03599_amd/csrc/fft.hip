@@ -37,7 +37,14 @@
 namespace {
 
 constexpr int FFT_THREADS = 256;
-constexpr int FFT_ELEMS = 1024;  // complex elements per LDS buffer of a line batch
+// Line batch of a work-group: about 512 complex elements per LDS buffer (more
+// work-groups per CU; 1024 and 2048 measured slower), but at least 8 lines
+// along the second axis, whose batch runs over consecutive i (8 x 16 bytes: whole
+// 128-byte segments).
+constexpr int FFT_ELEMS = 512;
+__host__ __device__ constexpr int line_batch(int LM, int axis) {
+  return FFT_ELEMS / LM >= (axis == 1 ? 8 : 1) ? FFT_ELEMS / LM : (axis == 1 ? 8 : 1);
+}
 
 __device__ inline cplx cj(cplx a, int c) { return c ? cconj(a) : a; }
 
@@ -196,7 +203,7 @@ __device__ inline void pcg_finish(const PcgHook& H, double* sh) {
 template <int LT, int AXIS, int SPLIT, int SIGN, int MODE>
 __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
   constexpr int LM = SPLIT ? 2 * LT : LT;          // line length in memory
-  constexpr int B = (FFT_ELEMS / LM) > 0 ? FFT_ELEMS / LM : 1;  // lines per work-group
+  constexpr int B = line_batch(LM, AXIS);  // lines per work-group
   constexpr int PL = LT + 1;                      // LDS pitch of a line
   __shared__ cplx buf0[(SPLIT ? 2 * B : B) * PL], buf1[(SPLIT ? 2 * B : B) * PL];
   __shared__ cplx roots_s[LT], twist_s[LT];  // the stages' twiddles and this layout's twist
@@ -712,7 +719,7 @@ int run_lines(pbr_ctx* c, const FftTables& T, bool blocked, int nb, int axis, in
     c->set_error("unsupported FFT length (2^a 3^b 5^c from the supported list, up to 256; blocks: n_l / 2)");
     return ST_EINVAL;
   }
-  const int B = std::max(1, FFT_ELEMS / LM);
+  const int B = line_batch(LM, axis);
   dim3 grid(ceil_div(A.nlines, B), 3, nb);
   if (nparts) *nparts = (int)(grid.x * 3);
   if (mode == 1 && (long)grid.x * 3 > part_cap) {
