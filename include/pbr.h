@@ -238,9 +238,22 @@ pbr_status pbr_eigs(pbr_ctx *c, const double kappa[3], int block, int nev,
  * blocks and merging their spectra (Sec. 6.1).  Each block starts with
  * nev_b = ceil(nev/4) + 4 eigenpairs; a block whose largest computed eigenvalue
  * lies below the merged nev-th value is recomputed with more eigenpairs until
- * every block certifies the cut.  Needs an even grid. */
+ * every block certifies the cut (at most 8 rounds); PBR_ENOCONV, with the
+ * merged values written, when a block stays uncertified.  Needs an even grid. */
 pbr_status pbr_eigs_merged(pbr_ctx *c, const double kappa[3], int nev, double shift,
                            const pbr_opts *opts, double *evals, pbr_stats *st);
+
+/* pbr_eigs_merged with the eigenvectors: the nev lowest eigenpairs of the full
+ * pencil from the four parity blocks (Corollary 4.2, same certification rule).
+ * evals: nev host doubles, ascending.  blocks: nev host ints, the parity block
+ * each eigenpair comes from (values equal across blocks are ordered by block).
+ * evecs: nev vectors of pbr_block_dim(c, 0) complex128 one after another
+ * (device memory if evecs_on_device, else host), vector t in block blocks[t]'s
+ * layout, M-normalised (v^H M_sigma v = 1); pbr_block_scatter places one in the
+ * full space.  These are the per-block pairs pbr_eig_grad takes. */
+pbr_status pbr_eigs_merged_vecs(pbr_ctx *c, const double kappa[3], int nev, double shift,
+                                const pbr_opts *opts, double *evals, int *blocks, void *evecs,
+                                int evecs_on_device, pbr_stats *st);
 
 /* Band structure along nk reduced wave vectors kappas (nk x 3 row-major host
  * doubles): evals[q*nev + t] is the t-th eigenvalue at kappa q.  blocked = 1
@@ -285,6 +298,22 @@ pbr_status pbr_band_paths(int ncells, pbr_ctx *const *ctxs, const int *nk,
 pbr_status pbr_eig_grad(pbr_ctx *c, const double kappa[3], int block, int nvec,
                         const double *lambda, const double *weight, const void *evecs,
                         int evecs_on_device, double *gC21, double *grho, int grad_on_device);
+
+/* The HIP stream (hipStream_t) the context orders its work on: the one given
+ * to pbr_create, or the context's own stream (created with default flags, so
+ * HIP orders it against the legacy null stream: work a caller issues on the
+ * null stream before a call runs before the call's kernels, and work issued
+ * after it runs after them).  NULL for a NULL context.  Callers time the
+ * library's kernels with events recorded on this stream. */
+void *pbr_stream(const pbr_ctx *c);
+
+/* Measurement support, not an operation of the method: copy `bytes` (a
+ * multiple of 16) from src to dst, both device memory on the context's device,
+ * with a plain streaming kernel on the context's stream (16-byte non-temporal
+ * loads and stores, no reuse).  Its rate is the copy reference the operator
+ * kernels' HBM rates are compared with.  PBR_EINVAL for NULL pointers or a bad
+ * byte count; src and dst must not overlap. */
+pbr_status pbr_copy_probe(pbr_ctx *c, const void *src, void *dst, long bytes);
 
 /* Message of the last failing call on c (or of the last failing pbr_create when
  * c is NULL).  The string lives until the next call on c. */

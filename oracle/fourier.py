@@ -148,6 +148,15 @@ def homogeneous_closed_form(dims, kappa, C, rho, A_lat=None):
     return np.sort(np.array(vals))
 
 
+def homogeneous_spectrum(dims, kappa, C, rho, A_lat=None):
+    """The same union as homogeneous_closed_form, for large grids: the symbol
+    matrices Bhat(m) C Bhat(m)^H of all modes at once (mode_matrices with a zero
+    shift) and a batched Hermitian eigensolve (Sec. 5.3; Appendix B).  Pinned
+    against the looped form on small grids."""
+    K = mode_matrices(dims, kappa, C, 1.0, 0.0, A_lat)
+    return np.sort(np.linalg.eigvalsh(K).ravel()) / rho
+
+
 def precond_dense(r, dims, kappa, block, C_ref, rho_ref, delta, A_lat=None):
     """z = Q^H (I_3 (x) T_xi) diag K(m)^-1 (I_3 (x) T_xi)^H Q r, literally.
 

@@ -248,6 +248,18 @@ void pbr_destroy(pbr_ctx* c) {
   delete c;
 }
 
+void* pbr_stream(const pbr_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+pbr_status pbr_copy_probe(pbr_ctx* c, const void* src, void* dst, long bytes) {
+  if (!c) return PBR_EINVAL;
+  if (!src || !dst || bytes < 0 || bytes % 16 != 0) {
+    c->set_error("copy probe: device pointers and a byte count that is a multiple of 16 expected");
+    return PBR_EINVAL;
+  }
+  (void)hipSetDevice(c->device);
+  return (pbr_status)launch_copy_probe(c, src, dst, bytes);
+}
+
 const char* pbr_last_error(const pbr_ctx* c) {
   if (!c) return g_create_error.c_str();
   return c->err.c_str();
@@ -647,6 +659,48 @@ pbr_status pbr_eigs_merged(pbr_ctx* c, const double kappa[3], int nev, double sh
   st = merged_eigs(c, kappa, nev, shift, o, evals, stats);
   if (stats)
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return (pbr_status)st;
+}
+
+pbr_status pbr_eigs_merged_vecs(pbr_ctx* c, const double kappa[3], int nev, double shift,
+                                const pbr_opts* opts, double* evals, int* blocks, void* evecs,
+                                int evecs_on_device, pbr_stats* stats) {
+  if (!c) return PBR_EINVAL;
+  const pbr_opts o = resolve_opts(opts);
+  int st = check_block(c, 0);
+  if (st == ST_OK) st = check_kappa(c, kappa);
+  if (st == ST_OK) st = check_opts(c, o);
+  if (st == ST_OK && (!evals || !blocks || !evecs || nev < 1 || !std::isfinite(shift))) {
+    c->set_error("evals, blocks and evecs must be non-NULL, nev >= 1, shift finite");
+    st = ST_EINVAL;
+  }
+  if (st == ST_OK) st = check_material(c);
+  if (st != ST_OK) return (pbr_status)st;
+  hipSetDevice(c->device);
+  if (!(shift > 0.0)) shift = pbr_default_shift(c);
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const long n3 = 3 * c->layout_nodes(0);
+  Staged ev;
+  if (evecs_on_device) {
+    ev.dev = (cplx*)evecs;
+  } else {
+    if ((st = dev_alloc(c, (void**)&ev.dev, sizeof(cplx) * n3 * (long)nev)) != ST_OK)
+      return (pbr_status)st;
+    ev.owned = true;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  st = merged_eigs(c, kappa, nev, shift, o, evals, stats, ev.dev, blocks);
+  if (stats)
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st != ST_OK && st != ST_ENOCONV) return (pbr_status)st;
+  if (!evecs_on_device) {
+    if (hipMemcpyAsync(evecs, ev.dev, sizeof(cplx) * n3 * nev, hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      c->set_error("copying eigenvectors to the host failed");
+      return PBR_EDEVICE;
+    }
+  }
   return (pbr_status)st;
 }
 

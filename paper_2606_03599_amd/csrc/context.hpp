@@ -221,17 +221,24 @@ struct LayoutRef {
 int launch_eig_grad(pbr_ctx* c, const Geo& g, int block, int nvec, const double* lam,
                     const double* w, const cplx* v, double* gC, double* grho);
 
+// streaming copy of `bytes` (a multiple of 16) on the context stream (probe.hip)
+int launch_copy_probe(pbr_ctx* c, const void* src, void* dst, long bytes);
+
 // solver drivers (solver.cpp)
 int ensure_work(pbr_ctx* c, int slot, int block);
 int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b, cplx* x,
               const pbr_opts& o, int* iters, int* conv);
 int lanczos_eigs(pbr_ctx* c, const double kappa[3], int block, int nev, double shift,
                  const pbr_opts& o, double* evals, cplx* evecs_dev, pbr_stats* st);
+// evecs_dev (optional, with blocks_out): the merged eigenpairs' block-layout
+// eigenvectors, nev x 3n/4 complex vector-major, and the block of each.
 int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const pbr_opts& o,
-                double* evals, pbr_stats* st);
+                double* evals, pbr_stats* st, cplx* evecs_dev = nullptr,
+                int* blocks_out = nullptr);
 // Blocked (certified merge) and full-space eigenvalues along nk wave vectors
 // (kappas: nk x 3, evals: nk x nev), up to PBR_KSLOTS k-points in lockstep.
 int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
-                const pbr_opts& o, double* evals, pbr_stats* st);
+                const pbr_opts& o, double* evals, pbr_stats* st, cplx* evecs_dev = nullptr,
+                int* blocks_out = nullptr);
 int full_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
               const pbr_opts& o, double* evals, pbr_stats* st);

@@ -854,13 +854,27 @@ void add_stats(pbr_stats* acc, const pbr_stats& one) {
 // another).  evals: nk x nev; stats summed over the k-points (nev_block of the
 // last one).
 int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
-                const pbr_opts& o, double* evals, pbr_stats* st) {
+                const pbr_opts& o, double* evals, pbr_stats* st, cplx* evecs_dev,
+                int* blocks_out) {
   const long dimb = 3 * (c->n / 4);
   int status = ST_OK;
   int last_nev_b[4] = {0, 0, 0, 0};
+  const bool want_vecs = evecs_dev != nullptr;
+  if (want_vecs && (nk != 1 || !blocks_out)) {
+    c->set_error("merged eigenvectors: one wave vector and a block index array expected");
+    return ST_EINVAL;
+  }
+  // eigenvectors of each block's latest solve (want_vecs only), freed on return
+  struct BlockVecs {
+    cplx* v[4] = {nullptr, nullptr, nullptr, nullptr};
+    int cap[4] = {0, 0, 0, 0};
+    ~BlockVecs() {
+      for (cplx* p : v) dev_free(p);
+    }
+  } bv;
   for (int k0 = 0; k0 < nk; k0 += PBR_KSLOTS) {
     const int gk = std::min(PBR_KSLOTS, nk - k0);
-    int nev_b[PBR_KSLOTS][4], need[PBR_KSLOTS];
+    int nev_b[PBR_KSLOTS][4], need[PBR_KSLOTS], flagged[PBR_KSLOTS] = {0, 0, 0, 0};
     std::vector<double> vals[PBR_KSLOTS][4];
     for (int q = 0; q < gk; ++q) {
       const double* kap = kappas + 3 * (k0 + q);
@@ -873,6 +887,7 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
       LayoutRef L[PBR_MAX_BATCH];
       int nevs[PBR_MAX_BATCH], rc[PBR_MAX_BATCH], qk[PBR_MAX_BATCH];
       double* ev[PBR_MAX_BATCH];
+      cplx* evp[PBR_MAX_BATCH] = {};
       pbr_stats part[PBR_MAX_BATCH];
       int np = 0;
       for (int q = 0; q < gk; ++q)
@@ -887,6 +902,16 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
           L[np].warm_slot = round > 0 ? q : (k0 > 0 ? PBR_KSLOTS - 1 : -1);
           nevs[np] = nev_b[q][b];
           ev[np] = vals[q][b].data();
+          if (want_vecs) {
+            if (bv.cap[b] < nev_b[q][b]) {
+              dev_free(bv.v[b]);
+              bv.v[b] = nullptr;
+              bv.cap[b] = 0;
+              PBR_TRY(dev_alloc(c, (void**)&bv.v[b], sizeof(cplx) * dimb * nev_b[q][b]));
+              bv.cap[b] = nev_b[q][b];
+            }
+            evp[np] = bv.v[b];
+          }
           qk[np] = q;
           rc[np] = ST_OK;
           ++np;
@@ -894,11 +919,12 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
       if (!np) break;
       std::memset(part, 0, sizeof(part));
       if (o.concurrent) {
-        PBR_TRY(lanczos_batch(c, np, L, nevs, shift, o, ev, nullptr, part, rc));
+        PBR_TRY(lanczos_batch(c, np, L, nevs, shift, o, ev, want_vecs ? evp : nullptr, part,
+                              rc));
       } else {
         for (int t = 0; t < np; ++t)
-          PBR_TRY(lanczos_batch(c, 1, L + t, nevs + t, shift, o, ev + t, nullptr, part + t,
-                                rc + t));
+          PBR_TRY(lanczos_batch(c, 1, L + t, nevs + t, shift, o, ev + t,
+                                want_vecs ? evp + t : nullptr, part + t, rc + t));
       }
       for (int t = 0; t < np; ++t) {
         if (st) add_stats(st, part[t]);
@@ -918,6 +944,7 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
         const double* kap = kappas + 3 * (k0 + q);
         const int nz = is_gamma(kap) ? 3 : 0;
         need[q] = 0;
+        flagged[q] = mask;
         for (int b = 0; b < 4; ++b)
           if (mask & (1 << b)) {
             const int nb =
@@ -929,7 +956,32 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
           }
       }
     }
+    // A block still flagged after the last round (or whose eigenpair count
+    // cannot grow further) may hide values below the merged cut: the merged
+    // values of that wave vector are not certified.
+    for (int q = 0; q < gk; ++q)
+      if (flagged[q]) {
+        c->set_error("block merge not certified at path point " + std::to_string(k0 + q) +
+                     ": a block's largest computed eigenvalue stays below the merged nev-th "
+                     "value");
+        status = ST_ENOCONV;
+      }
     for (int b = 0; b < 4; ++b) last_nev_b[b] = nev_b[gk - 1][b];
+    if (want_vecs) {
+      // the nev lowest of the union in ascending order (ties: lower block, then
+      // lower index first), each with its block and its block-layout eigenvector
+      std::vector<std::pair<double, std::pair<int, int>>> all;
+      for (int b = 0; b < 4; ++b)
+        for (int i = 0; i < nev_b[0][b]; ++i) all.push_back({vals[0][b][i], {b, i}});
+      std::sort(all.begin(), all.end());
+      for (int t = 0; t < nev; ++t) {
+        const int b = all[t].second.first, i = all[t].second.second;
+        blocks_out[t] = b;
+        PBR_HIP(c, hipMemcpyAsync(evecs_dev + (long)t * dimb, bv.v[b] + (long)i * dimb,
+                                  sizeof(cplx) * dimb, hipMemcpyDeviceToDevice, c->stream));
+      }
+      PBR_HIP(c, hipStreamSynchronize(c->stream));
+    }
   }
   if (st) {
     for (int b = 0; b < 4; ++b) st->nev_block[b] = last_nev_b[b];
@@ -942,8 +994,8 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
 }
 
 int merged_eigs(pbr_ctx* c, const double kappa[3], int nev, double shift, const pbr_opts& o,
-                double* evals, pbr_stats* st) {
-  return merged_path(c, 1, kappa, nev, shift, o, evals, st);
+                double* evals, pbr_stats* st, cplx* evecs_dev, int* blocks_out) {
+  return merged_path(c, 1, kappa, nev, shift, o, evals, st, evecs_dev, blocks_out);
 }
 
 // Full-space eigenvalues at nk wave vectors, up to PBR_KSLOTS in lockstep.

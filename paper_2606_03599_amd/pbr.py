@@ -4,7 +4,12 @@ Every function has the name of the C entry point it wraps and forwards to it
 through ctypes; all computation happens in the HIP library.  Vectors may be
 
 * torch tensors on the context's GPU (complex128, contiguous): passed by device
-  pointer with on_device = 1 and ordered on the context stream;
+  pointer with on_device = 1 and ordered on the context stream.  A Context takes
+  torch's current stream when that is not the default stream; under torch's
+  default (null) stream, whose handle is 0, the library creates its own stream
+  with default flags, which HIP orders against the null stream in issue order,
+  so torch work issued before a call completes before its kernels and work issued
+  after it waits for them.  Context.stream_handle() names the stream in use;
 * numpy arrays (complex128 / float64, C-contiguous): passed by host pointer with
   on_device = 0.
 
@@ -90,6 +95,10 @@ _SIGS = {
     "pbr_eigs_merged": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double,
                                        ctypes.POINTER(PbrOpts), _dp,
                                        ctypes.POINTER(PbrStats)]),
+    "pbr_eigs_merged_vecs": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double,
+                                            ctypes.POINTER(PbrOpts), _dp,
+                                            ctypes.POINTER(ctypes.c_int), _vp, ctypes.c_int,
+                                            ctypes.POINTER(PbrStats)]),
     "pbr_band_path": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.POINTER(PbrOpts), _dp,
                                      ctypes.POINTER(PbrStats)]),
@@ -98,6 +107,8 @@ _SIGS = {
                                       ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.POINTER(PbrOpts), ctypes.POINTER(_dp),
                                       ctypes.POINTER(PbrStats)]),
+    "pbr_stream": (_vp, [_vp]),
+    "pbr_copy_probe": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_long]),
     "pbr_last_error": (ctypes.c_char_p, [_vp]),
     "pbr_destroy": (None, [_vp]),
     "pbr_host_heev": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp]),
@@ -184,6 +195,23 @@ def pbr_create(n1, n2, n3, A_lat=None, device=0, stream=None):
 
 def pbr_destroy(ctx):
     lib().pbr_destroy(ctx)
+
+
+def pbr_stream(ctx):
+    """hipStream_t (as an int, 0 for the null stream) the context orders its work on."""
+    return lib().pbr_stream(ctx) or 0
+
+
+def pbr_copy_probe(ctx, src, dst):
+    """Streaming device copy src -> dst (torch tensors on the GPU, same byte size)."""
+    ps, os_, ks = _vec(src, np.float64)
+    pd, od, kd = _vec(dst, np.float64)
+    if not (os_ and od):
+        raise TypeError("the copy probe takes device tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    _check(ctx, lib().pbr_copy_probe(ctx, ps, pd, int(nbytes)))
 
 
 def pbr_last_error(ctx):
@@ -316,6 +344,25 @@ def pbr_eigs_merged(ctx, kappa, nev, shift=0.0, opts=None, raise_on_noconv=True)
     return ev, st
 
 
+def pbr_eigs_merged_vecs(ctx, kappa, nev, evecs, shift=0.0, opts=None, raise_on_noconv=True):
+    """Returns (evals (nev,), blocks (nev,) int, stats, evecs); evecs holds nev
+    block-layout vectors of pbr_block_dim(ctx, 0) complex (torch tensor on the
+    GPU or numpy array), vector t in block blocks[t]."""
+    kp, kk = _kappa(kappa)
+    ev = np.zeros(int(nev))
+    bl = np.zeros(int(nev), dtype=np.int32)
+    st = PbrStats()
+    o = opts if opts is not None else pbr_opts_default()
+    pe, oe, ke = _vec(evecs)
+    status = lib().pbr_eigs_merged_vecs(ctx, kp, int(nev), float(shift), ctypes.byref(o),
+                                        ev.ctypes.data_as(_dp),
+                                        bl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), pe, oe,
+                                        ctypes.byref(st))
+    if status != PBR_ENOCONV or raise_on_noconv:
+        _check(ctx, status)
+    return ev, bl, st, ke
+
+
 def pbr_band_path(ctx, kappas, nev, blocked=True, shift=0.0, opts=None, raise_on_noconv=True):
     ks = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64).reshape(-1, 3))
     ev = np.zeros((ks.shape[0], int(nev)))
@@ -415,6 +462,14 @@ class Context:
                 stream = None
         self.h = pbr_create(*self.dims, A_lat=A_lat, device=device, stream=stream)
 
+    def stream_handle(self):
+        """The hipStream_t the context launches on (events that time its kernels
+        are recorded on this stream; see pbr_stream)."""
+        return pbr_stream(self.h)
+
+    def copy_probe(self, src, dst):
+        pbr_copy_probe(self.h, src, dst)
+
     def close(self):
         if self.h:
             pbr_destroy(self.h)
@@ -471,6 +526,9 @@ class Context:
 
     def eigs_merged(self, kappa, nev, shift=0.0, opts=None):
         return pbr_eigs_merged(self.h, kappa, nev, shift, opts)
+
+    def eigs_merged_vecs(self, kappa, nev, evecs, shift=0.0, opts=None):
+        return pbr_eigs_merged_vecs(self.h, kappa, nev, evecs, shift, opts)
 
     def band_path(self, kappas, nev, blocked=True, shift=0.0, opts=None):
         return pbr_band_path(self.h, kappas, nev, blocked, shift, opts)

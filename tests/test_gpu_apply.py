@@ -14,6 +14,7 @@ from oracle import blocks as Bk, discretization as D, pointwise as P
 from synth import complex_gaussian, random_spd_field, two_phase_cell
 
 from gpu_util import log, make_ctx, rel, to_dev, to_host
+from paper_2606_03599_amd import pbr
 
 pytestmark = pytest.mark.gpu
 
@@ -187,3 +188,26 @@ def test_apply_n128_sampled():
         got = np.array([Yb[:, pos[idx[t]]] for t in sel])
         assert rel(got, y_pts[sel]) <= TOL, b
     ctx.close()
+
+
+def test_copy_probe_and_stream():
+    """The copy probe (the bench's copy-rate reference) copies exactly and
+    rejects bad sizes; pbr_stream names the stream the context launches on."""
+    import torch
+    ctx = pbr.Context((4, 4, 4))
+    a = torch.randn(1 << 20, dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)
+    ctx.copy_probe(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(pbr.PbrError) as e:
+        pbr._check(ctx.h, pbr.lib().pbr_copy_probe(ctx.h, a.data_ptr(), b.data_ptr(), 24))
+    assert e.value.status == pbr.PBR_EINVAL
+    # under torch's default stream the context owns a stream of its own
+    assert ctx.stream_handle() != 0
+    ctx.close()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx2 = pbr.Context((4, 4, 4))
+        assert ctx2.stream_handle() == s.cuda_stream
+        ctx2.close()

@@ -97,6 +97,42 @@ def test_eigenvectors_residual_and_M_normalised(n8):
         assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(A @ v)
 
 
+@pytest.mark.parametrize("point", ["k", "gamma"])
+def test_merged_eigs_with_vectors_n8(n8, point):
+    """pbr_eigs_merged_vecs: the merged values of the dense oracle, each with the
+    block it came from and an M-normalised eigenvector of that block's pencil."""
+    import torch
+    from oracle import blocks as Bk
+    g, ctx, C21, rho = n8
+    pt = g["points"][point]
+    dims = tuple(g["dims"])
+    nev = 12
+    V = torch.zeros((nev, 3 * 128), dtype=torch.complex128, device="cuda")
+    ev, blocks, st, V = ctx.eigs_merged_vecs(pt["kappa"], nev, V)
+    ref = np.array(pt["full_lowest"][:nev])
+    assert np.all(np.abs(ev - ref) <= TOL * np.abs(ref)), (ev, ref)
+    ev2, _ = ctx.eigs_merged(pt["kappa"], nev)
+    assert np.array_equal(ev, ev2)
+    Vh = to_host(V)
+    A = D.assemble_A(dims, pt["kappa"], C21)
+    M = D.assemble_M(rho)
+    for b in range(4):
+        blk_ref = np.array(pt["block_lowest"][b])
+        idx = np.nonzero(blocks == b)[0]
+        # the values attributed to block b are the lowest of block b's spectrum
+        assert np.all(np.abs(ev[idx] - blk_ref[:len(idx)]) <= TOL * np.abs(blk_ref[:len(idx)]))
+        Ab = Bk.block_operator(A, dims, b)
+        Mb = Bk.block_operator(M, dims, b)
+        for t in idx:
+            v = Vh[t]
+            assert abs(np.vdot(v, Mb @ v) - 1.0) < 1e-10
+            r = Ab @ v - ev[t] * (Mb @ v)
+            assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(Ab @ v)
+    host = np.zeros((nev, 3 * 128), dtype=np.complex128)
+    ev3, blocks3, _, host = ctx.eigs_merged_vecs(pt["kappa"], nev, host)
+    assert np.array_equal(ev3, ev) and np.array_equal(blocks3, blocks)
+
+
 def test_band_path_blocked_equals_full_n8(n8):
     g, ctx, C21, rho = n8
     ks, _ = sc_path(6)

@@ -118,6 +118,33 @@ def test_homogeneous_closed_form(A_lat):
 
 
 @pytest.mark.parametrize("A_lat", [None, "fcc"])
+@pytest.mark.parametrize("kappa", [KAPPA, (0.0, 0.0, 0.0), (0.5, 0.25, -0.3)])
+def test_homogeneous_spectrum_vectorised(A_lat, kappa):
+    """The batched closed form (used at n = 128) equals the dense spectrum of the
+    assembled operator, independently of the looped form it restates."""
+    Al = FCC if A_lat == "fcc" else None
+    dims = (4, 2, 6)
+    C = random_spd_stiffness(np.random.default_rng(7))
+    n = int(np.prod(dims))
+    C21 = np.tile(pack_c21(C), (n, 1))
+    ev = np.sort(np.linalg.eigvalsh(D.assemble_A(dims, kappa, C21, Al).toarray())) / 1.7
+    hs = F.homogeneous_spectrum(dims, kappa, C, 1.7, Al)
+    assert hs.shape == (3 * n,)
+    assert np.abs(ev - hs).max() <= 1e-13 * hs.max()
+    cf = F.homogeneous_closed_form((6, 4, 8), kappa, C, 1.7, Al)
+    assert np.abs(F.homogeneous_spectrum((6, 4, 8), kappa, C, 1.7, Al) - cf).max() <= \
+        1e-13 * cf.max()
+
+
+def test_homogeneous_spectrum_orbit_multiplicity():
+    """Every value of the homogeneous full spectrum on an even grid appears a
+    multiple of four times: K(m) is the same on each orbit of Eq. 5.3."""
+    C = random_spd_stiffness(np.random.default_rng(8))
+    hs = F.homogeneous_spectrum((8, 8, 8), KAPPA, C, 1.0)
+    assert np.abs(hs[0::4] - hs[3::4]).max() <= 1e-12 * hs.max()
+
+
+@pytest.mark.parametrize("A_lat", [None, "fcc"])
 def test_continuum_limit(A_lat):
     """Lowest three discrete eigenvalues -> Christoffel eigenvalues, error O(h^2)."""
     Al = np.eye(3) if A_lat is None else FCC
