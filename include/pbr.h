@@ -212,6 +212,22 @@ pbr_status pbr_apply_blocks(pbr_ctx *c, const double kappa[3], double s, const v
 pbr_status pbr_precond(pbr_ctx *c, const double kappa[3], int block, double shift,
                        const void *r, void *z, int on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pbr_precond
+ * on device pointers with no allocation of any kind.  Same arguments, kernels
+ * and result as pbr_precond with on_device = 1 (bit for bit); r and z are device
+ * memory on the context's device, work is ordered on the context's stream.
+ * The per-wave-vector tables the kernels read (roots, twists, mode phases of the
+ * three axes) are written by each call into a fixed array of 9 x 256 complex128
+ * (36,864 bytes) that every device the library runs on holds until the process
+ * ends, set up by pbr_create; hence every n_l must be at most 256 (PBR_EINVAL
+ * otherwise, before any work).  The array is shared by all contexts on a device
+ * and keeps the last call's contents: calls that overlap in time on one device
+ * (other streams, other host threads) race on it and must be serialised by the
+ * caller.  PBR_ESTATE before pbr_set_material. */
+pbr_status pbr_precond_noalloc(pbr_ctx *c, const double kappa[3], int block, double shift,
+                               const void *r, void *z);
+
 /* Solve (A_h(k) + shift M_h) x = b (block: A_sigma, M_sigma) by preconditioned
  * conjugate gradients from x = 0 (the inner solve of Sec. 6.1, Eq. 6.2).  Reads
  * the residual norm on the host every opts->check_every iterations.  Returns

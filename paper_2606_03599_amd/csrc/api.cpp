@@ -204,6 +204,14 @@ pbr_status pbr_create(pbr_ctx** out, int n1, int n2, int n3, const double* A_lat
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hpinned, sizeof(double) * PBR_PINNED);
   if (e != hipSuccess) {
     g_create_error = std::string("HIP device setup failed: ") + hipGetErrorString(e);
+    if (c->hpinned) (void)hipHostFree(c->hpinned);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return PBR_EDEVICE;
+  }
+  if (scratch_init(c) != ST_OK) {
+    g_create_error = c->err;
+    (void)hipHostFree(c->hpinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return PBR_EDEVICE;
@@ -553,6 +561,21 @@ pbr_status pbr_precond(pbr_ctx* c, const double kappa[3], int block, double shif
   if ((st = launch_precond(c, kappa, block, shift, sr.dev, sz.dev)) != ST_OK)
     return (pbr_status)st;
   return (pbr_status)stage_out(c, sz, z, n3, on_device);
+}
+
+pbr_status pbr_precond_noalloc(pbr_ctx* c, const double kappa[3], int block, double shift,
+                               const void* r, void* z) {
+  if (!c) return PBR_EINVAL;
+  int st = check_block(c, block);
+  if (st == ST_OK) st = check_kappa(c, kappa);
+  if (st == ST_OK && (!r || !z || !(shift > 0.0) || !std::isfinite(shift))) {
+    c->set_error("r, z must be non-NULL device pointers and shift > 0");
+    st = ST_EINVAL;
+  }
+  if (st == ST_OK) st = check_material(c);
+  if (st != ST_OK) return (pbr_status)st;
+  hipSetDevice(c->device);
+  return (pbr_status)launch_precond_noalloc(c, kappa, block, shift, (const cplx*)r, (cplx*)z);
 }
 
 pbr_status pbr_solve(pbr_ctx* c, const double kappa[3], int block, double shift, const void* b,

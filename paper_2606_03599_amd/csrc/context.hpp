@@ -114,6 +114,7 @@ struct pbr_ctx {
   LayoutWork work[5 * PBR_KSLOTS];   // [slot][natural, block 0..3]
 
   double* hpinned = nullptr;      // pinned host scratch (PBR_PINNED doubles)
+  cplx* scratch = nullptr;        // this device's fixed table array (pbr_precond_noalloc)
   PcgScalars* st_all = nullptr;   // device CG scalars of all work areas, contiguous
   // One captured chunk of fused PCG iterations, replayed while its launch
   // arguments (layouts, vectors, k, shift, chunk length) stay the same.
@@ -204,6 +205,11 @@ int launch_apply(pbr_ctx* c, const Geo& g, int block, double s, const cplx* x, c
 // z = preconditioner(r) in layout `block`
 int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift,
                    const cplx* r, cplx* z);
+// The same with the tables in the device's fixed scratch array (no allocation;
+// n_l <= 256), and the one-time lookup of that array's address per device.
+int launch_precond_noalloc(pbr_ctx* c, const double kappa[3], int block, double shift,
+                           const cplx* r, cplx* z);
+int scratch_init(pbr_ctx* c);
 // The preconditioner passes of one fused PCG iteration (five launches) for nb
 // layouts of one kind at once; P[t] names the layout (slot, block, kappa).
 int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift);

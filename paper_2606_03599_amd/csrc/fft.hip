@@ -28,6 +28,8 @@
 // Every 1D transform is a mixed radix-4/2/3/5 Stockham FFT in LDS on a batch of
 // lines; lines along j and k are batched over consecutive i for coalescing.
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "blas.hpp"
@@ -783,11 +785,12 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
 
 }  // namespace
 
-int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, const cplx* r,
+namespace {
+
+// The five passes of the preconditioner of one layout with the tables T.
+int precond_passes(pbr_ctx* c, const FftTables& T, int block, double shift, const cplx* r,
                    cplx* z) {
   const bool blocked = block >= 0;
-  PBR_TRY(ensure_tables(c, 0, blocked, kappa));
-  const FftTables& T = c->tables(0, blocked);
   const long N = c->layout_nodes(block);
   LineIO a{r, z, nullptr, PcgHook()}, b{z, z, nullptr, PcgHook()};
   SolveIO s{block, z, nullptr, nullptr, &T};
@@ -801,6 +804,81 @@ int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, c
   PBR_TRY(run_lines(c, T, blocked, 1, 1, +1, 0, &b0, 1.0, 0, nullptr));
   PBR_TRY(run_lines(c, T, blocked, 1, 0, +1, 0, &b1, 1.0 / (double)N, 0, nullptr));
   return ST_OK;
+}
+
+// Tables of pbr_precond_noalloc, for callers that cannot allocate: the roots,
+// twist and mode phases of the three axes (each at most SCRATCH_L entries),
+// rewritten by every call.  Each device holds its own copy; its address is
+// looked up once per device (scratch_init) and kernels are handed that address.
+constexpr int SCRATCH_L = 256;
+constexpr int SCRATCH_CPLX = 9 * SCRATCH_L;  // [axis][roots, twist, post][SCRATCH_L]
+static __device__ __align__(256) cplx scratch[SCRATCH_CPLX];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+cplx* g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+}  // namespace
+
+int scratch_init(pbr_ctx* c) {
+  if (c->device < 0 || c->device >= SCRATCH_DEVICES) {
+    c->set_error("device index beyond the no-allocation scratch table");
+    return ST_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[c->device]) {
+    void* ptr = nullptr;
+    PBR_HIP(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      c->set_error("hipGetSymbolAddress returned a null address for the scratch tables");
+      return ST_EDEVICE;
+    }
+    g_scratch_ptr[c->device] = (cplx*)ptr;
+  }
+  c->scratch = g_scratch_ptr[c->device];
+  return ST_OK;
+}
+
+int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, const cplx* r,
+                   cplx* z) {
+  const bool blocked = block >= 0;
+  PBR_TRY(ensure_tables(c, 0, blocked, kappa));
+  return precond_passes(c, c->tables(0, blocked), block, shift, r, z);
+}
+
+int launch_precond_noalloc(pbr_ctx* c, const double kappa[3], int block, double shift,
+                           const cplx* r, cplx* z) {
+  const bool blocked = block >= 0;
+  const int Lt[3] = {blocked ? c->n1 / 2 : c->n1, blocked ? c->n2 / 2 : c->n2,
+                     blocked ? c->n3 / 2 : c->n3};
+  const int nf[3] = {c->n1, c->n2, c->n3};
+  for (int l = 0; l < 3; ++l)
+    if (nf[l] > SCRATCH_L) {
+      c->set_error("pbr_precond_noalloc: grid size " + std::to_string(nf[l]) +
+                   " beyond the fixed scratch tables (n_l <= 256)");
+      return ST_EINVAL;
+    }
+  if (!c->scratch) {
+    c->set_error("pbr_precond_noalloc: scratch tables not set up for this context");
+    return ST_ESTATE;
+  }
+  FftTables T;
+  for (int l = 0; l < 3; ++l) {
+    const double phi = 2.0 * M_PI * kappa[l];
+    T.kappa[l] = kappa[l];
+    T.L[l] = Lt[l];
+    T.roots[l] = c->scratch + (3 * l + 0) * SCRATCH_L;
+    T.twist[l] = c->scratch + (3 * l + 1) * SCRATCH_L;
+    T.post[l] = c->scratch + (3 * l + 2) * SCRATCH_L;
+    hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream, Lt[l],
+                       0.0, 1, T.roots[l]);
+    hipLaunchKernelGGL(table_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream, Lt[l],
+                       phi, 0, T.twist[l]);
+    hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream, nf[l],
+                       phi, 2, T.post[l]);
+  }
+  PBR_HIP(c, hipGetLastError());
+  return precond_passes(c, T, block, shift, r, z);
 }
 
 int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift) {

@@ -86,6 +86,8 @@ _SIGS = {
                                     ctypes.c_int, _vp, _vp, ctypes.c_int]),
     "pbr_precond": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
                                    ctypes.c_int]),
+    "pbr_precond_noalloc": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp,
+                                           _vp]),
     "pbr_solve": (ctypes.c_int, [_vp, _dp, ctypes.c_int, ctypes.c_double, _vp, _vp,
                                  ctypes.POINTER(PbrOpts), ctypes.POINTER(PbrStats),
                                  ctypes.c_int]),
@@ -305,6 +307,17 @@ def pbr_precond(ctx, kappa, block, shift, r, z):
     return kz
 
 
+def pbr_precond_noalloc(ctx, kappa, block, shift, r, z):
+    """pbr_precond without any allocation; r, z device tensors."""
+    pr, orr, kr = _vec(r)
+    pz, oz, kz = _vec(z)
+    if not (orr and oz):
+        raise TypeError("pbr_precond_noalloc takes device tensors only")
+    kp, kk = _kappa(kappa)
+    _check(ctx, lib().pbr_precond_noalloc(ctx, kp, int(block), float(shift), pr, pz))
+    return z
+
+
 def pbr_solve(ctx, kappa, block, shift, b, x, opts=None, raise_on_noconv=True):
     kp, kk = _kappa(kappa)
     pb, ob, kb = _vec(b)
@@ -517,6 +530,9 @@ class Context:
 
     def precond(self, kappa, block, shift, r, z):
         return pbr_precond(self.h, kappa, block, shift, r, z)
+
+    def precond_noalloc(self, kappa, block, shift, r, z):
+        return pbr_precond_noalloc(self.h, kappa, block, shift, r, z)
 
     def solve(self, kappa, block, shift, b, x, opts=None):
         return pbr_solve(self.h, kappa, block, shift, b, x, opts)
