@@ -166,6 +166,17 @@ int pbr_material_palette(const pbr_ctx *c);
  * differently.  PBR_EINVAL for a NULL context or any other shape. */
 pbr_status pbr_set_stencil_shape(pbr_ctx *c, int ti, int tj);
 
+/* Pass structure of the FFT-diagonal preconditioner (pbr_precond and the fused
+ * inner PCG) in a parity block: 0 (the default) or 3 = three passes over the
+ * block vector where the block box has them (n1 = n2 with n1/2 one of 2, 3, 4,
+ * 5, 6, 8, 10, 12, 15, 16, 20, 24, 30, 32, 40, 48, 64): both in-plane axes of a
+ * plane at once, the third axis with the per-mode solves, the in-plane inverse;
+ * 5 = five passes, one per axis and direction plus the solve (every other box,
+ * and the full space, always uses five).  The two structures compute the same
+ * operator (Sec. 5.1-5.4) and agree to rounding.  Takes effect at the next
+ * call.  PBR_EINVAL for a NULL context or another value. */
+pbr_status pbr_set_precond_passes(pbr_ctx *c, int passes);
+
 /* Override the constant reference material of the preconditioner
  * (K(m) = Bhat(m) C_ref Bhat(m)^H + shift * rho_ref * I_3, Sec. 5.3-5.4): C21_ref
  * is 21 host doubles in the C21 order, rho_ref > 0. */

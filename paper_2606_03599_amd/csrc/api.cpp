@@ -232,12 +232,14 @@ void pbr_destroy(pbr_ctx* c) {
     dev_free(M.idx);
   }
   dev_free(c->pal);
-  for (auto& T : c->fft)
+  for (auto& T : c->fft) {
     for (int l = 0; l < 3; ++l) {
       dev_free(T.twist[l]);
       dev_free(T.post[l]);
       dev_free(T.roots[l]);
     }
+    for (cplx* t : T.postp) dev_free(t);
+  }
   for (auto& W : c->work) {
     cplx* vs[] = {W.x, W.r, W.p, W.q, W.z, W.b, W.w, W.t, W.U, W.U2, W.small};
     for (cplx* v : vs) dev_free(v);
@@ -369,6 +371,17 @@ pbr_status pbr_set_stencil_shape(pbr_ctx* c, int ti, int tj) {
     c->pin_tj = tj;
     ++c->mat_gen;  // captured PCG graphs hold the old launch shape
   }
+  return PBR_OK;
+}
+
+pbr_status pbr_set_precond_passes(pbr_ctx* c, int passes) {
+  if (!c) return PBR_EINVAL;
+  if (passes != 0 && passes != 3 && passes != 5) {
+    c->set_error("precond passes: 0 (automatic), 3 or 5 expected");
+    return PBR_EINVAL;
+  }
+  c->precond_passes = passes;
+  c->mat_gen += 1;  // captured PCG graphs hold the old pass structure
   return PBR_OK;
 }
 

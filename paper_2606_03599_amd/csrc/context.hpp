@@ -53,6 +53,10 @@ struct FftTables {
   cplx* twist[3] = {nullptr, nullptr, nullptr};   // e^{-i x phi_l / L_l}, x in [0,L_l)
   cplx* post[3] = {nullptr, nullptr, nullptr};    // e^{-i beta_q} per frequency (block y2/y3)
   cplx* roots[3] = {nullptr, nullptr, nullptr};   // e^{-2 pi i k / L_l}
+  // blocks with the three-pass preconditioner: e^{i alpha}, e^{i beta},
+  // e^{i gamma} in the digit-reversed order its transforms leave along i', y2
+  // and y3 (lengths n1/2, n2/2, n3/2)
+  cplx* postp[3] = {nullptr, nullptr, nullptr};
   int L[3] = {0, 0, 0};
 };
 
@@ -94,6 +98,7 @@ struct pbr_ctx {
   } stencil_tune[PBR_TUNE_SLOTS];
   int stencil_tune_next = 0;
   int pin_ti = 0, pin_tj = 0;  // stencil tile shape pinned by pbr_set_stencil_shape (0: tuned)
+  int precond_passes = 0;      // pbr_set_precond_passes: 0 automatic, 3 or 5
   hipStream_t stream = nullptr;
   bool own_stream = false;
 

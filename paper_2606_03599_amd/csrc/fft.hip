@@ -19,14 +19,24 @@
 // preconditioner is: sub-lattice DFTs, fold, two 3x3 solves, unfold, inverse.
 //
 // Passes (each reads and writes the 3-component vector once; the first
-// pass reads r, every later pass works in place on z):
+// pass reads r, every later pass works in place on z).  A parity block whose
+// box has them takes three:
+//   1. plane pass: one (y3, component) plane of both sub-lattices per
+//      work-group, transformed along i' and y2 in place in LDS;
+//   2. y3 axis forward, fold + 3x3 solves + unfold per orbit pair, y3 axis
+//      inverse, in place in LDS;
+//   3. plane pass inverse, times 1/N;
+// the in-place transforms (plane_r1 plans) leave the modes in digit-reversed
+// order along each axis, which the solve reads through permuted phase tables.
+// The full space, and blocks without such a box, take five:
 //   1. i axis: length-n1 lines, split into even/odd half lines for a block;
 //   2. j (y2) axis;
-//   3. k (y3) axis forward, fold + 3x3 Cholesky solves + unfold per mode,
-//      k axis inverse -- all in LDS;
+//   3. k (y3) axis forward, fold + 3x3 solves + unfold per mode, k axis
+//      inverse -- all in LDS;
 //   4. j axis inverse;   5. i axis inverse, times 1/N.
-// Every 1D transform is a mixed radix-4/2/3/5 Stockham FFT in LDS on a batch of
-// lines; lines along j and k are batched over consecutive i for coalescing.
+// There every 1D transform is a mixed radix-4/2/3/5 Stockham FFT in LDS on a
+// batch of lines; lines along j and k are batched over consecutive i for
+// coalescing.
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -96,6 +106,64 @@ __device__ inline void small_dft(cplx* v) {
     v[1] = cadd(m, iu);
     v[2] = csub(m, iu);
   }
+}
+
+// DFT of R = 1..6, 8 values held in registers (same convention as small_dft):
+// R = 6 and 8 as two interleaved halves of size 3 / 4 combined with e^{SIGN 2 pi i k / R}.
+template <int R, int SIGN>
+__device__ inline void reg_dft(cplx* v) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 6) {
+    cplx e[3] = {v[0], v[2], v[4]}, o[3] = {v[1], v[3], v[5]};
+    small_dft<3, SIGN>(e);
+    small_dft<3, SIGN>(o);
+    const double h = 0.86602540378443864676;  // sin(pi / 3)
+    const cplx o1 = cmul(mk(0.5, SIGN * h), o[1]), o2 = cmul(mk(-0.5, SIGN * h), o[2]);
+    v[0] = cadd(e[0], o[0]);
+    v[3] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[4] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[5] = csub(e[2], o2);
+  } else if constexpr (R == 8) {
+    cplx e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    small_dft<4, SIGN>(e);
+    small_dft<4, SIGN>(o);
+    const double c = 0.70710678118654752440;  // cos(pi / 4)
+    const cplx o1 = cmul(mk(c, SIGN * c), o[1]);
+    const cplx o2 = (SIGN < 0) ? mk(o[2].y, -o[2].x) : mk(-o[2].y, o[2].x);  // SIGN i o2
+    const cplx o3 = cmul(mk(-c, SIGN * c), o[3]);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  } else {
+    small_dft<R, SIGN>(v);
+  }
+}
+
+// In-place plan of a length L = R1 * R2 for the plane pass: a strided step of
+// R1-point DFTs (elements R2 n1 + n2) with twiddles, then a contiguous step of
+// R2-point DFTs; the result sits in digit-reversed order, position R2 k1 + k2
+// holding frequency k1 + R1 k2 (plane_freq).  R1 = L, R2 = 1 for a single step;
+// 0 when L has no such split.
+__host__ __device__ constexpr int plane_r1(int L) {
+  switch (L) {
+    case 2: case 3: case 4: case 5: case 6: case 8: return L;
+    case 9: case 12: case 15: case 16: case 20: case 25: return L % 5 == 0 ? 5 : (L % 4 == 0 ? 4 : 3);
+    case 10: return 5;
+    case 18: case 24: case 30: case 36: return 6;
+    case 32: case 40: case 48: case 64: return 8;
+    default: return 0;
+  }
+}
+__host__ __device__ inline int plane_freq(int pos, int L) {
+  const int r1 = plane_r1(L), r2 = L / r1;
+  return pos / r2 + r1 * (pos % r2);
 }
 
 // Radix plan of a length 2^a 3^b 5^c, fixed at compile time: radix-4 stages,
@@ -359,11 +427,268 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Plane pass of a parity block: both in-plane axes in one pass.  A work-group
+// holds one (y3, component) plane of the block, both sub-lattices (2 L0 x L1
+// complex; 128 KB at n = 128), in LDS and transforms it in place along i' and
+// y2 for each sub-lattice (plane_r1 plans; the forward transform leaves both
+// axes in digit-reversed order, which the mode solve reads through permuted
+// mode-phase tables, and the inverse takes that order back to natural).
+// MODE 0: plain transform in -> out (scale on the inverse).  MODE 1 (forward):
+// first PCG pass, r -= alpha q (or r = b, x = 0 at init) with the |r|^2
+// partials, then the transform of r.  MODE 2 (inverse): last PCG pass, every
+// work-group finishes (r, z) from the mode solve's partials, beta = (r, z) /
+// (r, z)_old; out p = scale z + beta p and x += alpha p (the old p).
+// Scalars: alpha uses rz_next (the previous last pass's (r, z)); the first
+// work-group of the first pass moves it to rz, which the last pass divides by.
+// ---------------------------------------------------------------------------
+constexpr int PLANE_THREADS = 512;
+
+struct PlaneArgs {
+  int L3;            // planes (y3 extent)
+  long N;            // block nodes
+  double scale;
+  const cplx* __restrict__ roots0;  // e^{-2 pi i t / L0}
+  const cplx* __restrict__ roots1;  // e^{-2 pi i t / L1}
+  struct {
+    const cplx* in;
+    cplx* out;
+    const cplx* tw0;  // twist along i' (length L0), this layout's k
+    const cplx* tw1;  // twist along y2 (length L1)
+    PcgHook h;
+  } b[PBR_MAX_BATCH];
+};
+
+// LDS geometry of a plane: row (p, y2) of L0 elements, pitch L0 + 1; the two
+// sub-lattice planes SP apart with SP = 8 mod 16 (elements) so that lanes
+// alternating between sub-lattices fall in different banks.
+__host__ __device__ constexpr int plane_sp(int L0, int L1) {
+  return L1 * (L0 + 1) + ((8 - (L1 * (L0 + 1)) % 16) + 16) % 16;
+}
+
+// One strided step (R1-point DFTs of elements R2 n1 + n2 of each line, then the
+// twiddle W_L^(n2 k1)) or one contiguous step (R2-point DFTs of elements
+// R2 k1 + k2, with the twiddle W_L^(-n2 k1) applied after them on the inverse),
+// in place on nl lines.  Line l starts at lbase(l); consecutive elements of a
+// line are ES apart.
+template <int L, int ES, int SIGN, bool STRIDED, class LB>
+__device__ inline void plane_step(cplx* sm, const cplx* __restrict__ roots, int nl, LB lbase) {
+  constexpr int R1 = plane_r1(L), R2 = L / R1;
+  constexpr int R = STRIDED ? R1 : R2;   // DFT size of this step
+  constexpr int NT = STRIDED ? R2 : R1;  // DFTs per line
+  if constexpr (R == 1) return;
+#pragma unroll 1
+  for (int t = threadIdx.x; t < nl * NT; t += blockDim.x) {
+    const int l = t % nl, j = t / nl;
+    cplx* base = sm + lbase(l);
+    cplx v[R];
+    if constexpr (STRIDED) {
+      // forward: x[R2 n1 + j] -> DFT over n1 -> times W^(j k1) -> position R2 k1 + j
+      // inverse: position R2 k1 + j -> DFT over k1 -> x[R2 n1 + j]
+#pragma unroll
+      for (int a = 0; a < R; ++a) v[a] = base[(R2 * a + j) * ES];
+      reg_dft<R, SIGN>(v);
+      if (SIGN < 0 && R2 > 1) {
+#pragma unroll
+        for (int a = 1; a < R; ++a) v[a] = cmul(v[a], roots[(j * a) % L]);
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) base[(R2 * a + j) * ES] = v[a];
+    } else {
+      // forward: contiguous group j (= k1): DFT over n2 -> position R2 j + k2
+      // inverse: DFT over k2 -> times W^(-n2 j) -> position R2 j + n2
+#pragma unroll
+      for (int a = 0; a < R; ++a) v[a] = base[(R2 * j + a) * ES];
+      reg_dft<R, SIGN>(v);
+      if (SIGN > 0 && R1 > 1) {
+#pragma unroll
+        for (int a = 1; a < R; ++a) v[a] = cmul(v[a], cconj(roots[(j * a) % L]));
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) base[(R2 * j + a) * ES] = v[a];
+    }
+  }
+}
+
+// Both steps of the transform of every row (axis i') or every column (axis y2).
+template <int L0, int L1, int SIGN, int AXIS>
+__device__ inline void plane_axis(cplx* sm, const cplx* __restrict__ roots) {
+  constexpr int RP = L0 + 1, SP = plane_sp(L0, L1);
+  if constexpr (AXIS == 0) {
+    // lines: rows (p, y2), line-fastest lanes (rows RP apart spread the banks)
+    auto lb = [](int l) { return (l / L1) * SP + (l % L1) * RP; };
+    if (SIGN < 0) {
+      plane_step<L0, 1, SIGN, true>(sm, roots, 2 * L1, lb);
+      __syncthreads();
+      plane_step<L0, 1, SIGN, false>(sm, roots, 2 * L1, lb);
+    } else {
+      plane_step<L0, 1, SIGN, false>(sm, roots, 2 * L1, lb);
+      __syncthreads();
+      plane_step<L0, 1, SIGN, true>(sm, roots, 2 * L1, lb);
+    }
+  } else {
+    // lines: columns (p, i'), consecutive lanes on consecutive i'
+    auto lb = [](int l) { return (l / L0) * SP + (l % L0); };
+    if (SIGN < 0) {
+      plane_step<L1, RP, SIGN, true>(sm, roots, 2 * L0, lb);
+      __syncthreads();
+      plane_step<L1, RP, SIGN, false>(sm, roots, 2 * L0, lb);
+    } else {
+      plane_step<L1, RP, SIGN, false>(sm, roots, 2 * L0, lb);
+      __syncthreads();
+      plane_step<L1, RP, SIGN, true>(sm, roots, 2 * L0, lb);
+    }
+  }
+  __syncthreads();
+}
+
+template <int L0, int L1, int SIGN, int MODE>
+__global__ void __launch_bounds__(PLANE_THREADS) plane_kernel(PlaneArgs A) {
+  constexpr int NEL = 2 * L0 * L1;  // plane elements, both sub-lattices
+  constexpr int N1 = 2 * L0;        // i extent of the block box
+  constexpr int RP = L0 + 1, SP = plane_sp(L0, L1);
+  constexpr int PER = (NEL + PLANE_THREADS - 1) / PLANE_THREADS;
+  __shared__ cplx sm[2 * SP];
+  __shared__ cplx roots0_s[L0], roots1_s[L1];
+  __shared__ double red[PLANE_THREADS / 64 + 1];
+  const PcgHook& H = A.b[blockIdx.z].h;
+  const cplx* in_ = A.b[blockIdx.z].in;
+  cplx* out_ = A.b[blockIdx.z].out;
+  const cplx* __restrict__ tw0 = A.b[blockIdx.z].tw0;
+  const cplx* __restrict__ tw1 = A.b[blockIdx.z].tw1;
+  PcgScalars* st = H.st;
+  const int comp = blockIdx.y;
+  const bool first_wg = blockIdx.x == 0 && blockIdx.y == 0;
+  const long base = comp * A.N + (long)blockIdx.x * NEL;
+  auto lds_of = [](int e) {  // element e of the plane in memory -> LDS position
+    const int i = e % N1, y2 = e / N1;
+    return (i & 1) * SP + y2 * RP + (i >> 1);
+  };
+  // Operands first (MODE 1: r, q or b; MODE 2: the transformed z, the old p, x;
+  // MODE 0: the input), then the scalars, so their latencies overlap.
+  cplx va[PER], vb[PER], vc[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * PLANE_THREADS;
+    va[k] = vb[k] = vc[k] = mk(0, 0);
+    if (e >= NEL) continue;
+    if (MODE == 1) {
+      if (H.init) {
+        va[k] = H.b[base + e];
+      } else {
+        va[k] = H.r[base + e];
+        vb[k] = H.q[base + e];
+      }
+    } else {
+      va[k] = in_[base + e];
+      if (MODE == 2 && !H.init) vb[k] = out_[base + e];  // old p
+    }
+  }
+  for (int t = threadIdx.x; t < L0; t += blockDim.x) roots0_s[t] = A.roots0[t];
+  for (int t = threadIdx.x; t < L1; t += blockDim.x) roots1_s[t] = A.roots1[t];
+  if (st && !(MODE == 1 && H.init) && st->done) return;  // uniform per work-group
+  double alpha = 0.0, beta = 0.0;
+  if (MODE == 1) {
+    if (H.init) {
+      if (first_wg && threadIdx.x == 0) {
+        st->tol2 = H.tol2;
+        st->iters = 0;
+        st->done = 0;
+        st->alpha = st->beta = st->pq = 0.0;
+      }
+    } else {
+      const double pq = block_sum_array(H.red_in, H.red_n, red);
+      if (!(pq > 0.0)) {  // breakdown: the operator is not positive on p
+        if (first_wg && threadIdx.x == 0) {
+          st->pq = pq;
+          st->done = 2;
+        }
+        return;
+      }
+      alpha = st->rz_next / pq;
+      if (first_wg && threadIdx.x == 0) {
+        st->pq = pq;
+        st->alpha = alpha;
+        st->rz = st->rz_next;
+      }
+    }
+  } else if (MODE == 2) {
+    const double rz = block_sum_array(H.red_in, H.red_n, red) * H.inv_n;
+    alpha = st->alpha;
+    beta = H.init ? 0.0 : rz / st->rz;
+    if (first_wg && threadIdx.x == 0) {
+      st->rz_next = rz;
+      st->beta = beta;
+    }
+  }
+  // into LDS (forward: r update and twist first)
+  double rr = 0.0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * PLANE_THREADS;
+    if (e >= NEL) continue;
+    cplx x = va[k];
+    if (MODE == 1) {
+      if (H.init) {
+        H.r[base + e] = x;
+        H.x[base + e] = mk(0, 0);
+      } else {
+        x = cfma(-alpha, vb[k], x);
+        H.r[base + e] = x;
+      }
+      rr = fma(x.x, x.x, fma(x.y, x.y, rr));
+    }
+    if (SIGN < 0) {
+      const int i = e % N1, y2 = e / N1;
+      x = cmul(x, cmul(tw0[i >> 1], tw1[y2]));
+    }
+    sm[lds_of(e)] = x;
+  }
+  if (MODE == 1) {
+    const double s2 = block_sum_all(rr, red);
+    if (threadIdx.x == 0) H.part_out[comp * gridDim.x + blockIdx.x] = s2;
+  }
+  if (MODE == 2 && !H.init) {
+    // x is requested once z sits in LDS (its registers are free), so the
+    // transform hides the latency
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + k * PLANE_THREADS;
+      if (e < NEL) vc[k] = H.x[base + e];
+    }
+  }
+  __syncthreads();
+  if (SIGN < 0) {
+    plane_axis<L0, L1, SIGN, 0>(sm, roots0_s);
+    plane_axis<L0, L1, SIGN, 1>(sm, roots1_s);
+  } else {
+    plane_axis<L0, L1, SIGN, 1>(sm, roots1_s);
+    plane_axis<L0, L1, SIGN, 0>(sm, roots0_s);
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * PLANE_THREADS;
+    if (e >= NEL) continue;
+    cplx x = sm[lds_of(e)];
+    if (SIGN > 0) {
+      const int i = e % N1, y2 = e / N1;
+      x = cmul(x, cconj(cmul(tw0[i >> 1], tw1[y2])));
+    }
+    if (MODE == 2 && !H.init) {
+      out_[base + e] = cfma(beta, vb[k], cscale(A.scale, x));
+      H.x[base + e] = cfma(alpha, vb[k], vc[k]);
+    } else {
+      out_[base + e] = SIGN > 0 ? cscale(A.scale, x) : x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Pass 3: k axis forward, per-mode solve (with the orbit fold for a block),
 // k axis inverse.
 // ---------------------------------------------------------------------------
 struct SolveArgs {
   int L1, L2, L3;
+  int nb;  // layouts of the launch
   long N;
   const cplx* __restrict__ roots;  // length-L3 roots
   double cf[3][5];
@@ -373,6 +698,9 @@ struct SolveArgs {
     cplx* data;
     PcgScalars* st;   // fused PCG: skip once converged, write (r, z) partials
     double* part_out;
+    const double* rr_in;  // fused PCG after a plane pass: |r|^2 partials to finish
+    int rr_n;             // (every work-group sums them; the first records the test)
+    int init;
     int a, c;         // block class bits
     const cplx* twist;  // e^{-i y phi3 / L3} of this layout's k
     const cplx* e1;     // e^{i alpha_m} = e^{i (phi1 + 2 pi m)/n1}, m < n1
@@ -404,11 +732,11 @@ __device__ inline void mode_half_symbols(const SolveArgs& S, cplx Ea, cplx Eb, c
   }
 }
 
-// x = K^-1 b, K = Bhat C_ref Bhat^H + shift rho_ref I_3 for the symbols e
-// (Sec. 5.3-5.4).  K is Hermitian positive definite; it is inverted through
-// its adjugate (one division, no square roots).
-__device__ inline void symbol_solve(const SolveArgs& S, const cplx e[3], const cplx b[3],
-                                    cplx x[3]) {
+// K^-1 for the symbols e, K = Bhat C_ref Bhat^H + shift rho_ref I_3
+// (Sec. 5.3-5.4), as 9 doubles: the real diagonal (0, 1, 2) and the upper
+// entries (0,1), (0,2), (1,2) (re, im at 3..8).  K is Hermitian positive
+// definite; it is inverted through its adjugate (one division, no square roots).
+__device__ inline void symbol_inverse(const SolveArgs& S, const cplx e[3], double kinv[9]) {
   // K = Bhat C Bhat^H with Bhat's rows (Voigt columns, symbol) sparse:
   //   u1: (11, e1) (13, e3) (12, e2);  u2: (22, e2) (23, e3) (12, e1);
   //   u3: (33, e3) (23, e2) (13, e1)
@@ -454,9 +782,30 @@ __device__ inline void symbol_solve(const SolveArgs& S, const cplx e[3], const c
   const cplx A12 = csub(cmulc(d, ee), cscale(a, f));   // conj(d) e - a f
   const double det = fma(a, A00, fma(d.x, A01.x, fma(d.y, A01.y, fma(ee.x, A02.x, ee.y * A02.y))));
   const double id = 1.0 / det;
-  x[0] = cscale(id, cadd(cscale(A00, b[0]), cadd(cmul(A01, b[1]), cmul(A02, b[2]))));
-  x[1] = cscale(id, cadd(cmulc(A01, b[0]), cadd(cscale(A11, b[1]), cmul(A12, b[2]))));
-  x[2] = cscale(id, cadd(cmulc(A02, b[0]), cadd(cmulc(A12, b[1]), cscale(A22, b[2]))));
+  kinv[0] = id * A00;
+  kinv[1] = id * A11;
+  kinv[2] = id * A22;
+  kinv[3] = id * A01.x;
+  kinv[4] = id * A01.y;
+  kinv[5] = id * A02.x;
+  kinv[6] = id * A02.y;
+  kinv[7] = id * A12.x;
+  kinv[8] = id * A12.y;
+}
+
+// x = K^-1 b for K^-1 in the 9-double form of symbol_inverse.
+__device__ inline void inverse_apply(const double ki[9], const cplx b[3], cplx x[3]) {
+  const cplx A01 = mk(ki[3], ki[4]), A02 = mk(ki[5], ki[6]), A12 = mk(ki[7], ki[8]);
+  x[0] = cadd(cscale(ki[0], b[0]), cadd(cmul(A01, b[1]), cmul(A02, b[2])));
+  x[1] = cadd(cmulc(A01, b[0]), cadd(cscale(ki[1], b[1]), cmul(A12, b[2])));
+  x[2] = cadd(cmulc(A02, b[0]), cadd(cmulc(A12, b[1]), cscale(ki[2], b[2])));
+}
+
+__device__ inline void symbol_solve(const SolveArgs& S, const cplx e[3], const cplx b[3],
+                                    cplx x[3]) {
+  double ki[9];
+  symbol_inverse(S, e, ki);
+  inverse_apply(ki, b, x);
 }
 
 // i-values per work-group of the solve pass: 1536 complex per LDS buffer gives
@@ -475,26 +824,36 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   __shared__ cplx buf0[NL * PT], buf1[NL * PT];
   __shared__ cplx roots_s[L3T], twist_s[L3T], e3_s[L3T], e1_s[BI];
   __shared__ double red[FFT_THREADS / 64 + 1];
-  cplx* const data = S.b[blockIdx.y].data;
-  PcgScalars* const st = S.b[blockIdx.y].st;
-  double* const part_out = S.b[blockIdx.y].part_out;
-  const int ca = S.b[blockIdx.y].a, cc = S.b[blockIdx.y].c;
-  const cplx* __restrict__ e2 = S.b[blockIdx.y].e2;
+  // One-dimensional grid of tiles x layouts.  Work-group g runs on XCD g mod 8;
+  // each XCD takes a contiguous range of (tile, layout) indices, layout fastest
+  // (neighbouring tiles of a layout read neighbouring 128-byte runs together).
+  long lin;
+  {
+    const long T = (long)gridDim.x, g = blockIdx.x, x = g % 8, j = g / 8;
+    lin = x * (T / 8) + min(x, T % 8) + j;
+  }
+  const int lay = (int)(lin % S.nb);
+  const int tile = (int)(lin / S.nb);
+  cplx* const data = S.b[lay].data;
+  PcgScalars* const st = S.b[lay].st;
+  double* const part_out = S.b[lay].part_out;
+  const int ca = S.b[lay].a, cc = S.b[lay].c;
+  const cplx* __restrict__ e2 = S.b[lay].e2;
   const int groups_i = (S.L1 + BI - 1) / BI;
-  const int q = blockIdx.x / groups_i;
-  const int i0 = (blockIdx.x % groups_i) * BI;
+  const int q = tile / groups_i;
+  const int i0 = (tile % groups_i) * BI;
   const int bi = min(BI, S.L1 - i0);
   const long kstride = (long)S.L1 * S.L2;
   const long base = i0 + (long)S.L1 * q;
   // tables of this work-group in LDS: twiddles, twist, e^{i gamma_r}, and
   // e^{i alpha} of its i-values (block: of its BI/2 sub-lattice pairs)
   {
-    const cplx* __restrict__ e1g = S.b[blockIdx.y].e1;
+    const cplx* __restrict__ e1g = S.b[lay].e1;
     const int e1o = BLK ? (i0 >> 1) : i0;
     for (int t = threadIdx.x; t < L3T; t += blockDim.x) {
       roots_s[t] = S.roots[t];
-      twist_s[t] = S.b[blockIdx.y].twist[t];
-      e3_s[t] = S.b[blockIdx.y].e3[t];
+      twist_s[t] = S.b[lay].twist[t];
+      e3_s[t] = S.b[lay].e3[t];
     }
     for (int t = threadIdx.x; t < (BLK ? bi / 2 : bi); t += blockDim.x) e1_s[t] = e1g[e1o + t];
   }
@@ -502,7 +861,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   // twist from global memory)
   const cplx* __restrict__ twist = twist_s;
   const cplx* __restrict__ e3 = e3_s;
-  const cplx* __restrict__ twist_g = S.b[blockIdx.y].twist;
+  const cplx* __restrict__ twist_g = S.b[lay].twist;
   for (int w = threadIdx.x; w < NL * L3T; w += blockDim.x) {
     const int y = w / NL;
     const int rem = w - y * NL;
@@ -513,6 +872,23 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   }
   // (the operands are requested before the convergence flag is read)
   if (st && st->done) return;  // uniform per work-group
+  if (const double* rr_in = S.b[lay].rr_in) {
+    // |r|^2 of this iteration and the convergence test, reduced in the same
+    // order by every work-group, so all of them take the same decision
+    const double v = block_sum_array(rr_in, S.b[lay].rr_n, red);
+    const int init = S.b[lay].init;
+    const bool conv = init ? (v == 0.0) : (v <= st->tol2 * st->bb);
+    if (tile == 0 && threadIdx.x == 0) {
+      st->rr = v;
+      if (init) {
+        st->bb = v;
+      } else {
+        st->iters += 1;
+      }
+      if (conv) st->done = 1;
+    }
+    if (conv) return;  // uniform per work-group
+  }
   __syncthreads();
   cplx* f = fft_stages<L3T, PT, 0, 1, -1>(roots_s, buf0, buf1, NL);
   cplx* g = (f == buf0) ? buf1 : buf0;
@@ -540,7 +916,6 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     const int o20 = ca & 1, o30 = (ca + cc) & 1;
     for (int w = threadIdx.x; w < (bi / 2) * L3T; w += blockDim.x) {
       const int dp = w / L3T, r = w - dp * L3T;
-      const int m1p = (i0 >> 1) + dp;
       const cplx Ea = e1_s[dp], Eg = e3[r];
       // T_p = e^{-i(o2 beta + o3 gamma)}: conj(Eb)^o2 conj(Eg)^o3
       const cplx cb = cconj(Eb), cg = cconj(Eg);
@@ -577,7 +952,7 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
   }
   if (part_out) {
     const double v = block_sum_all(rz, red);
-    if (threadIdx.x == 0) part_out[blockIdx.x] = v;
+    if (threadIdx.x == 0) part_out[tile] = v;
   }
   __syncthreads();
   const cplx* res = fft_stages<L3T, PT, 0, 1, +1>(roots_s, g, f, NL);
@@ -588,6 +963,147 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
     if (di < bi)
       data[comp * S.N + base + di + y * kstride] =
           cmul(res[(comp * BI + di) * PT + y], cconj(twist[y]));
+  }
+}
+
+// Mode-solve pass of the three-pass block structure.  A work-group takes bi
+// consecutive i (both sub-lattices, bi / 2 orbit pairs; a contiguous run of
+// 16 bi bytes per line), one y2 position q and all L3 positions r of the three
+// components, transforms them in place along r (plane_r1 plan; the mode order
+// along r is then digit-reversed, as it already is along i' and y2 after the
+// plane pass), folds each orbit pair, solves the two 3x3 systems of its
+// symbols, unfolds, transforms back and writes in place.  Also finishes |r|^2 and the convergence test (rr_in) and
+// writes the (r, z) partials, like fft_solve_kernel.
+constexpr int SOLVE_THREADS = 512;
+// i-values per work-group (at most) for third axes longer than 32: 16 (50 KB of
+// LDS, three work-groups per CU) measured 4 % faster on the path at n = 128
+// than 32 (100 KB, one per CU)
+constexpr int SOLVE_BIM = 16;
+
+template <int L3T, int BIM>
+__global__ void __launch_bounds__(SOLVE_THREADS) solve_plane_kernel(SolveArgs S, int bi) {
+  constexpr int PT = L3T + 1;  // LDS pitch of a line along r
+  __shared__ cplx sm[3 * BIM * PT];
+  __shared__ cplx roots_s[L3T], e3_s[L3T], e1_s[BIM / 2];
+  __shared__ double red[SOLVE_THREADS / 64 + 1];
+  long lin;  // XCD-aware numbering of (tile, layout), as in fft_solve_kernel
+  {
+    const long T = (long)gridDim.x, g = blockIdx.x, x = g % 8, j = g / 8;
+    lin = x * (T / 8) + min(x, T % 8) + j;
+  }
+  const int lay = (int)(lin % S.nb);
+  const int tile = (int)(lin / S.nb);
+  cplx* const data = S.b[lay].data;
+  PcgScalars* const st = S.b[lay].st;
+  const int ca = S.b[lay].a, cc = S.b[lay].c;
+  const int groups_i = S.L1 / bi;
+  const int q = tile / groups_i;
+  const int i0 = (tile % groups_i) * bi;
+  const long kstride = (long)S.L1 * S.L2;
+  const long base = i0 + (long)S.L1 * q;
+  const int nel = 3 * bi * L3T;
+  constexpr int PER = (3 * BIM * L3T + SOLVE_THREADS - 1) / SOLVE_THREADS;
+  const cplx* __restrict__ twist_g = S.b[lay].twist;
+  cplx v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * SOLVE_THREADS;
+    v[k] = mk(0, 0);
+    if (e < nel) {
+      const int di = e % bi, rest = e / bi, r = rest % L3T, comp = rest / L3T;
+      v[k] = data[comp * S.N + base + di + r * kstride];
+    }
+  }
+  for (int t = threadIdx.x; t < L3T; t += blockDim.x) {
+    roots_s[t] = S.roots[t];
+    e3_s[t] = S.b[lay].e3[t];
+  }
+  for (int t = threadIdx.x; t < bi / 2; t += blockDim.x) e1_s[t] = S.b[lay].e1[(i0 >> 1) + t];
+  if (st && st->done) return;  // uniform per work-group
+  if (const double* rr_in = S.b[lay].rr_in) {
+    const double vv = block_sum_array(rr_in, S.b[lay].rr_n, red);
+    const int init = S.b[lay].init;
+    const bool conv = init ? (vv == 0.0) : (vv <= st->tol2 * st->bb);
+    if (tile == 0 && threadIdx.x == 0) {
+      st->rr = vv;
+      if (init) {
+        st->bb = vv;
+      } else {
+        st->iters += 1;
+      }
+      if (conv) st->done = 1;
+    }
+    if (conv) return;  // uniform per work-group
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * SOLVE_THREADS;
+    if (e < nel) {
+      const int di = e % bi, rest = e / bi, r = rest % L3T, comp = rest / L3T;
+      sm[(comp * bi + di) * PT + r] = cmul(v[k], twist_g[r]);
+    }
+  }
+  __syncthreads();
+  const int nl = 3 * bi;
+  auto lb = [](int l) { return l * PT; };
+  plane_step<L3T, 1, -1, true>(sm, roots_s, nl, lb);
+  __syncthreads();
+  plane_step<L3T, 1, -1, false>(sm, roots_s, nl, lb);
+  __syncthreads();
+  const cplx Eb = S.b[lay].e2[q];
+  const int o20 = ca & 1, o30 = (ca + cc) & 1;
+  double rz = 0.0;
+  for (int w = threadIdx.x; w < (bi / 2) * L3T; w += blockDim.x) {
+    const int dp = w / L3T, r = w - dp * L3T;
+    const cplx Ea = e1_s[dp], Eg = e3_s[r];
+    const cplx cb = cconj(Eb), cg = cconj(Eg);
+    const cplx one = mk(1.0, 0.0);
+    const cplx T0 = cmul(o20 ? cb : one, o30 ? cg : one);
+    const cplx T1 = cmul(o20 ? one : cb, o30 ? one : cg);
+    const cplx t1e = cmulc(Ea, T1);  // T1 e^{-i alpha}
+    cplx c0[3], c1[3], z0[3], z1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const cplx v0 = cmul(T0, sm[(a * bi + 2 * dp) * PT + r]);
+      const cplx v1 = cmul(t1e, sm[(a * bi + 2 * dp + 1) * PT + r]);
+      c0[a] = cadd(v0, v1);
+      c1[a] = csub(v0, v1);
+    }
+    // m1 = m1' and m1 = m1' + n1/2 (alpha + pi: -Ea) share the half symbols
+    cplx h[3], ep[3], em[3];
+    mode_half_symbols(S, Ea, Eb, Eg, h);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      ep[m] = mk(S.cf[m][0] + h[m].x, h[m].y);
+      em[m] = mk(S.cf[m][0] - h[m].x, -h[m].y);
+    }
+    symbol_solve(S, ep, c0, z0);
+    symbol_solve(S, em, c1, z1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rz = fma(c0[a].x, z0[a].x, fma(c0[a].y, z0[a].y, rz));
+      rz = fma(c1[a].x, z1[a].x, fma(c1[a].y, z1[a].y, rz));
+      sm[(a * bi + 2 * dp) * PT + r] = cmulc(T0, cadd(z0[a], z1[a]));
+      sm[(a * bi + 2 * dp + 1) * PT + r] = cmulc(t1e, csub(z0[a], z1[a]));
+    }
+  }
+  if (double* part_out = S.b[lay].part_out) {
+    const double vv = block_sum_all(rz, red);
+    if (threadIdx.x == 0) part_out[tile] = vv;
+  }
+  __syncthreads();
+  plane_step<L3T, 1, +1, false>(sm, roots_s, nl, lb);
+  __syncthreads();
+  plane_step<L3T, 1, +1, true>(sm, roots_s, nl, lb);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * SOLVE_THREADS;
+    if (e < nel) {
+      const int di = e % bi, rest = e / bi, r = rest % L3T, comp = rest / L3T;
+      data[comp * S.N + base + di + r * kstride] =
+          cmul(sm[(comp * bi + di) * PT + r], cconj(twist_g[r]));
+    }
   }
 }
 
@@ -605,6 +1121,19 @@ __global__ void table_kernel(int L, double phi, int kind, cplx* out) {
   sincos(ang, &s, &c);
   out[t] = mk(c, s);
 }
+
+// Mode phases e^{i (phi + 2 pi f) / n} in the digit-reversed order the plane
+// pass leaves along an axis of length L (f = plane_freq(t, L), t < L).
+__global__ void perm_phase_kernel(int L, int n, double phi, cplx* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L) return;
+  const double ang = (phi + 2.0 * M_PI * (double)plane_freq(t, L)) / (double)n;
+  double sn, cs;
+  sincos(ang, &sn, &cs);
+  out[t] = mk(cs, sn);
+}
+
+bool plane_pass(const pbr_ctx* c);
 
 // Tables of a layout kind (natural: slot 0; parity blocks, which share the box
 // shape: slot 1): for each transform length Lt[l] (axis 0 of a block: n1/2) the
@@ -624,6 +1153,12 @@ int ensure_tables(pbr_ctx* c, int slot, bool blocked, const double kappa[3]) {
                          Lt[l], 0.0, 1, T.roots[l]);
     }
   }
+  const bool perm = blocked && plane_pass(c);
+  for (int l = 0; perm && l < 3; ++l)
+    if (!T.postp[l]) {
+      PBR_TRY(dev_alloc(c, (void**)&T.postp[l], sizeof(cplx) * Lt[l]));
+      T.kappa[0] = 1e300;  // (re)build every table below
+    }
   if (T.kappa[0] != kappa[0] || T.kappa[1] != kappa[1] || T.kappa[2] != kappa[2]) {
     for (int l = 0; l < 3; ++l) {
       const double phi = 2.0 * M_PI * kappa[l];
@@ -631,6 +1166,9 @@ int ensure_tables(pbr_ctx* c, int slot, bool blocked, const double kappa[3]) {
                          Lt[l], phi, 0, T.twist[l]);
       hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream,
                          nf[l], phi, 2, T.post[l]);
+      if (T.postp[l])
+        hipLaunchKernelGGL(perm_phase_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0,
+                           c->stream, Lt[l], nf[l], phi, T.postp[l]);
       T.kappa[l] = kappa[l];
     }
   }
@@ -733,13 +1271,107 @@ int run_lines(pbr_ctx* c, const FftTables& T, bool blocked, int nb, int axis, in
   return ST_OK;
 }
 
+typedef void (*PlaneKernel)(PlaneArgs);
+
+#define PBR_PLANE_LENGTHS(X) \
+  X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(30) X(32) X(40) X(48) X(64)
+
+template <int SIGN, int MODE>
+PlaneKernel plane_kernel_for(int L0, int L1) {
+  if (L0 != L1) return nullptr;
+  switch (L0) {
+#define PBR_CASE(n) \
+  case n:           \
+    return plane_kernel<n, n, SIGN, MODE>;
+    PBR_PLANE_LENGTHS(PBR_CASE)
+#undef PBR_CASE
+    default:
+      return nullptr;
+  }
+}
+
+// Whether the block preconditioner runs as three passes (plane, mode solve,
+// plane): the block box has a plane kernel and the setting allows it.
+bool plane_length(int L) {
+  switch (L) {
+#define PBR_CASE(n) \
+  case n:           \
+    return true;
+    PBR_PLANE_LENGTHS(PBR_CASE)
+#undef PBR_CASE
+    default:
+      return false;
+  }
+}
+
+bool plane_pass(const pbr_ctx* c) {
+  if (c->precond_passes == 5 || !c->even) return false;
+  return plane_kernel_for<-1, 1>(c->n1 / 2, c->n2 / 2) != nullptr && plane_length(c->n3 / 2);
+}
+
+// One plane pass over nb parity-block layouts: sign -1 forward (mode 0 or 1),
+// +1 inverse (mode 0 or 2).  *nparts receives the partials per layout a mode-1
+// launch writes.
+struct PlaneIO {
+  const cplx* in;
+  cplx* out;
+  const FftTables* T;
+  PcgHook h;
+};
+
+int run_plane(pbr_ctx* c, int nb, int sign, int mode, const PlaneIO* io, double scale,
+              long part_cap, int* nparts) {
+  const int L0 = c->n1 / 2, L1 = c->n2 / 2, L3 = c->n3 / 2;
+  PlaneKernel k = nullptr;
+  if (sign < 0)
+    k = mode == 1 ? plane_kernel_for<-1, 1>(L0, L1) : plane_kernel_for<-1, 0>(L0, L1);
+  else
+    k = mode == 2 ? plane_kernel_for<1, 2>(L0, L1) : plane_kernel_for<1, 0>(L0, L1);
+  if (!k) {
+    c->set_error("no plane pass for this block box");
+    return ST_EINVAL;
+  }
+  PlaneArgs A;
+  A.L3 = L3;
+  A.N = c->layout_nodes(0);
+  A.scale = scale;
+  A.roots0 = io[0].T->roots[0];
+  A.roots1 = io[0].T->roots[1];
+  for (int t = 0; t < nb; ++t) {
+    A.b[t].in = io[t].in;
+    A.b[t].out = io[t].out;
+    A.b[t].tw0 = io[t].T->twist[0];
+    A.b[t].tw1 = io[t].T->twist[1];
+    A.b[t].h = io[t].h;
+  }
+  if (nparts) *nparts = 3 * L3;
+  if (mode == 1 && 3L * L3 > part_cap) {
+    c->set_error("grid too large for the PCG partial buffers");
+    return ST_EINVAL;
+  }
+  hipLaunchKernelGGL(k, dim3(L3, 3, nb), dim3(PLANE_THREADS), 0, c->stream, A);
+  PBR_HIP(c, hipGetLastError());
+  return ST_OK;
+}
+
 struct SolveIO {
   int block;
   cplx* data;
   PcgScalars* st;
   double* part_out;
   const FftTables* T;  // this layout's k-point tables
+  bool perm = false;   // input left by the plane pass: digit-reversed i' and y2
+  const double* rr_in = nullptr;  // |r|^2 partials to finish (fused PCG after a plane pass)
+  int rr_n = 0;
+  int init = 0;
 };
+
+void fill_symbol_args(const pbr_ctx* c, double shift, SolveArgs& S) {
+  for (int m = 0; m < 3; ++m)
+    for (int d = 0; d < 5; ++d) S.cf[m][d] = c->cf[m][d];
+  for (int qq = 0; qq < 21; ++qq) S.Cref[qq] = c->Cref[qq];
+  S.shift_rho = shift * c->rho_ref;
+}
 
 int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift, long part_cap,
               int* nparts) {
@@ -750,10 +1382,8 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
   S.L3 = blocked ? c->n3 / 2 : c->n3;
   S.N = c->layout_nodes(blocked ? 0 : -1);
   S.roots = T.roots[2];
-  for (int m = 0; m < 3; ++m)
-    for (int d = 0; d < 5; ++d) S.cf[m][d] = c->cf[m][d];
-  for (int qq = 0; qq < 21; ++qq) S.Cref[qq] = c->Cref[qq];
-  S.shift_rho = shift * c->rho_ref;
+  S.nb = nb;
+  fill_symbol_args(c, shift, S);
   for (int t = 0; t < nb; ++t) {
     S.b[t].data = io[t].data;
     S.b[t].st = io[t].st;
@@ -761,9 +1391,43 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
     S.b[t].a = io[t].block >= 0 ? io[t].block >> 1 : 0;
     S.b[t].c = io[t].block >= 0 ? io[t].block & 1 : 0;
     S.b[t].twist = io[t].T->twist[2];
-    S.b[t].e1 = io[t].T->post[0];
-    S.b[t].e2 = io[t].T->post[1];
-    S.b[t].e3 = io[t].T->post[2];
+    S.b[t].e1 = io[t].perm ? io[t].T->postp[0] : io[t].T->post[0];
+    S.b[t].e2 = io[t].perm ? io[t].T->postp[1] : io[t].T->post[1];
+    S.b[t].e3 = io[t].perm ? io[t].T->postp[2] : io[t].T->post[2];
+    S.b[t].rr_in = io[t].rr_in;
+    S.b[t].rr_n = io[t].rr_n;
+    S.b[t].init = io[t].init;
+  }
+  if (io[0].perm) {
+    // three-pass structure: every axis in digit-reversed mode order
+    typedef void (*PlaneSolveKernel)(SolveArgs, int);
+    PlaneSolveKernel k = nullptr;
+    switch (S.L3) {
+#define PBR_CASE(n)                                        \
+  case n:                                                  \
+    k = solve_plane_kernel<n, (n > 32 ? SOLVE_BIM : 32)>; \
+    break;
+      PBR_PLANE_LENGTHS(PBR_CASE)
+#undef PBR_CASE
+      default:
+        break;
+    }
+    const int bim = S.L3 > 32 ? SOLVE_BIM : 32;
+    int bi = bim;
+    while (bi > 2 && S.L1 % bi) bi >>= 1;
+    if (!k || S.L1 % bi) {
+      c->set_error("no mode-solve pass for this block box");
+      return ST_EINVAL;
+    }
+    const long nwg = (long)(S.L1 / bi) * S.L2;
+    if (nparts) *nparts = (int)nwg;
+    if (io[0].part_out && nwg > part_cap) {
+      c->set_error("grid too large for the PCG partial buffers");
+      return ST_EINVAL;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)(nwg * nb)), dim3(SOLVE_THREADS), 0, c->stream, S, bi);
+    PBR_HIP(c, hipGetLastError());
+    return ST_OK;
   }
   const SolveKernel k = blocked ? solve_kernel<1>(S.L3) : solve_kernel<0>(S.L3);
   if (!k) {
@@ -778,7 +1442,7 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
     c->set_error("grid too large for the PCG partial buffers");
     return ST_EINVAL;
   }
-  hipLaunchKernelGGL(k, dim3((unsigned)nwg, nb), dim3(FFT_THREADS), 0, c->stream, S);
+  hipLaunchKernelGGL(k, dim3((unsigned)(nwg * nb)), dim3(FFT_THREADS), 0, c->stream, S);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
@@ -787,11 +1451,21 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
 
 namespace {
 
-// The five passes of the preconditioner of one layout with the tables T.
+// The passes of the preconditioner of one layout with the tables T: three for
+// a block with a plane pass (T then holds the permuted mode phases), else five.
 int precond_passes(pbr_ctx* c, const FftTables& T, int block, double shift, const cplx* r,
                    cplx* z) {
   const bool blocked = block >= 0;
   const long N = c->layout_nodes(block);
+  if (blocked && plane_pass(c)) {
+    PlaneIO f{r, z, &T, PcgHook()}, v{z, z, &T, PcgHook()};
+    SolveIO s{block, z, nullptr, nullptr, &T};
+    s.perm = true;
+    PBR_TRY(run_plane(c, 1, -1, 0, &f, 1.0, 0, nullptr));
+    PBR_TRY(run_solve(c, true, 1, &s, shift, 0, nullptr));
+    PBR_TRY(run_plane(c, 1, +1, 0, &v, 1.0 / (double)N, 0, nullptr));
+    return ST_OK;
+  }
   LineIO a{r, z, nullptr, PcgHook()}, b{z, z, nullptr, PcgHook()};
   SolveIO s{block, z, nullptr, nullptr, &T};
   LineIO a0 = a, b0 = b, b1 = b;
@@ -811,7 +1485,8 @@ int precond_passes(pbr_ctx* c, const FftTables& T, int block, double shift, cons
 // rewritten by every call.  Each device holds its own copy; its address is
 // looked up once per device (scratch_init) and kernels are handed that address.
 constexpr int SCRATCH_L = 256;
-constexpr int SCRATCH_CPLX = 9 * SCRATCH_L;  // [axis][roots, twist, post][SCRATCH_L]
+// [axis][roots, twist, post][SCRATCH_L], then the permuted phases of the 3 axes
+constexpr int SCRATCH_CPLX = 12 * SCRATCH_L;
 static __device__ __align__(256) cplx scratch[SCRATCH_CPLX];
 
 constexpr int SCRATCH_DEVICES = 64;
@@ -876,6 +1551,11 @@ int launch_precond_noalloc(pbr_ctx* c, const double kappa[3], int block, double 
                        phi, 0, T.twist[l]);
     hipLaunchKernelGGL(table_kernel, dim3(ceil_div(nf[l], 256)), dim3(256), 0, c->stream, nf[l],
                        phi, 2, T.post[l]);
+    if (blocked && plane_pass(c)) {
+      T.postp[l] = c->scratch + (9 + l) * SCRATCH_L;
+      hipLaunchKernelGGL(perm_phase_kernel, dim3(ceil_div(Lt[l], 256)), dim3(256), 0, c->stream,
+                         Lt[l], nf[l], phi, T.postp[l]);
+    }
   }
   PBR_HIP(c, hipGetLastError());
   return precond_passes(c, T, block, shift, r, z);
@@ -888,6 +1568,7 @@ int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift)
   }
   const bool blocked = P[0].block >= 0;
   for (int t = 0; t < nb; ++t) PBR_TRY(ensure_tables(c, P[t].slot, blocked, P[t].kappa));
+  const bool planar = blocked && plane_pass(c);
   const FftTables& T0 = c->tables(P[0].slot, blocked);
   const long N = c->layout_nodes(P[0].block);
   const long cap = P[0].part_cap;
@@ -921,6 +1602,27 @@ int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift)
     io5[t] = LineIO{P[t].z, P[t].pout, T.twist[0], h};  // p = z + beta p, x += alpha p
     io5[t].h.x = P[t].x;
     sio[t] = SolveIO{P[t].block, P[t].z, P[t].st, P[t].part_rz, &T};
+  }
+  if (planar) {
+    // three passes: plane (r update, forward i' and y2), mode solve (finishes
+    // |r|^2 and the test, third axis, fold, solves, (r, z) partials), plane
+    // (finishes (r, z) and beta, inverse y2 and i', p and x updates)
+    PlaneIO pa[PBR_MAX_BATCH], pc[PBR_MAX_BATCH];
+    for (int t = 0; t < nb; ++t) {
+      const FftTables& T = c->tables(P[t].slot, blocked);
+      pa[t] = PlaneIO{nullptr, P[t].z, &T, io1[t].h};
+      pc[t] = PlaneIO{P[t].z, P[t].pout, &T, io5[t].h};
+      pc[t].h.red_in = P[t].part_rz;
+      sio[t].perm = true;
+      sio[t].rr_in = P[t].part_rr;
+      sio[t].init = P[t].init;
+    }
+    PBR_TRY(run_plane(c, nb, -1, 1, pa, 1.0, cap, &n_rr));
+    for (int t = 0; t < nb; ++t) sio[t].rr_n = n_rr;
+    PBR_TRY(run_solve(c, blocked, nb, sio, shift, cap, &n_rz));
+    for (int t = 0; t < nb; ++t) pc[t].h.red_n = n_rz;
+    PBR_TRY(run_plane(c, nb, +1, 2, pc, 1.0 / (double)N, cap, nullptr));
+    return ST_OK;
   }
   PBR_TRY(run_lines(c, T0, blocked, nb, 0, -1, 1, io1, 1.0, cap, &n_rr));
   for (int t = 0; t < nb; ++t) io2[t].h.red_n = n_rr;

@@ -114,3 +114,24 @@ def test_merged_eigs_homogeneous_n128(homog128, kappa):
     assert err.max() <= 1e-9
     # four-fold: each value once per block
     assert np.abs(ev[0::4] - ev[3::4]).max() <= 1e-9 * ev.max()
+
+
+@pytest.mark.parametrize("passes", [0, 5])
+def test_pcg_n128_block(cell128, passes):
+    """The inner PCG of the benchmark (block 1 at n = 128, the fused iteration
+    with three or five preconditioner passes): the solution's residual computed
+    by the oracle's operator is within the inner tolerance."""
+    import torch
+    from oracle import blocks as Bk, pointwise as P
+    ctx, Cref, rref, delta = cell128
+    ctx.set_precond_passes(passes)
+    C21, rho, _ = two_phase_cell(DIMS, radius=0.35, seed=0)
+    b = complex_gaussian(3 * N ** 3 // 4, seed=77)
+    bd = to_dev(b)
+    xd, st = ctx.solve(KAPPA, 1, delta, bd, torch.zeros_like(bd))
+    x = Bk.scatter(to_host(xd), DIMS, 1)
+    r = Bk.gather(P.apply_A(x, DIMS, KAPPA, C21, rho, s=delta), DIMS, 1)
+    e = rel(r, b)
+    log(f"pcg n=128 block 1 passes={passes}: {st.pcg_iters_total} iterations, residual {e:.2e}")
+    ctx.set_precond_passes(0)
+    assert st.converged == 1 and e <= 2e-12

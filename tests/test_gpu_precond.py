@@ -47,6 +47,29 @@ def test_precond_matches_oracle(dims, A_lat):
     ctx.close()
 
 
+@pytest.mark.parametrize("dims", [(4, 4, 4), (8, 8, 6), (10, 10, 10), (12, 12, 8), (16, 16, 16),
+                                  (20, 20, 12), (24, 24, 24), (30, 30, 6), (32, 32, 16),
+                                  (40, 40, 8), (48, 48, 4), (64, 64, 8)])
+@pytest.mark.parametrize("passes", [3, 5])
+def test_block_precond_pass_structures(dims, passes):
+    """Blocks with n1 = n2 run the three-pass structure (whole planes, in-place
+    transforms in digit-reversed order) unless five passes are asked for; both
+    match the oracle, at a generic wave vector, at a zone corner and at Gamma."""
+    log(f"block precond dims={dims} passes={passes}")
+    C21, rho = random_spd_field(dims, seed=12)
+    n = int(np.prod(dims))
+    ctx = make_ctx(dims, C21, rho)
+    ctx.set_precond_passes(passes)
+    Cref, rref = F.reference_material(C21, rho)
+    for kap in (KAPPA, (0.5, 0.5, 0.5), (0.0, 0.0, 0.0)):
+        for b in range(4):
+            rb = complex_gaussian(3 * n // 4, seed=60 + b)
+            zb_or = F.precond_fft(rb, dims, kap, b, Cref, rref, 1.3)
+            zb = to_host(ctx.precond(kap, b, 1.3, to_dev(rb), to_dev(np.zeros_like(rb))))
+            assert rel(zb, zb_or) <= TOL, (kap, b)
+    ctx.close()
+
+
 def test_precond_reference_override():
     dims = (8, 4, 4)
     C21, rho = random_spd_field(dims, seed=1)

@@ -15,12 +15,13 @@ KAPPA = (0.15, 0.05, 0.10)
 
 
 @pytest.mark.parametrize("kappa", [KAPPA, (0.0, 0.0, 0.0)])
-@pytest.mark.parametrize("precond", [1, 0])
-def test_pcg_matches_direct_n8(kappa, precond):
+@pytest.mark.parametrize("precond,passes", [(1, 0), (1, 5), (0, 0)])
+def test_pcg_matches_direct_n8(kappa, precond, passes):
     dims = (8, 8, 8)
-    log(f"pcg n=8 kappa={kappa} precond={precond}")
+    log(f"pcg n=8 kappa={kappa} precond={precond} passes={passes}")
     C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
     ctx = make_ctx(dims, C21, rho)
+    ctx.set_precond_passes(passes)
     delta = D.default_shift(C21)
     o = pbr.pbr_opts_default()
     o.precond = precond
@@ -39,11 +40,13 @@ def test_pcg_matches_direct_n8(kappa, precond):
     ctx.close()
 
 
-def test_pcg_residual_n64_block():
+@pytest.mark.parametrize("passes", [0, 5])
+def test_pcg_residual_n64_block(passes):
     dims = (64, 64, 64)
-    log("pcg n=64 block residual")
+    log(f"pcg n=64 block residual, preconditioner passes {passes}")
     C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
     ctx = make_ctx(dims, C21, rho)
+    ctx.set_precond_passes(passes)
     delta = D.default_shift(C21)
     b = complex_gaussian(3 * 64 ** 3, seed=5)
     bb = Bk.gather(b, dims, 2)
