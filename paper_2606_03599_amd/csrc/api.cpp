@@ -209,7 +209,7 @@ pbr_status pbr_create(pbr_ctx** out, int n1, int n2, int n3, const double* A_lat
     delete c;
     return PBR_EDEVICE;
   }
-  if (scratch_init(c) != ST_OK) {
+  if (scratch_init(c) != ST_OK || preload_kernels(c) != ST_OK) {
     g_create_error = c->err;
     (void)hipHostFree(c->hpinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);

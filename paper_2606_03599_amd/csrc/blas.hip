@@ -365,6 +365,13 @@ unsigned grid_for(long n) {
 
 }  // namespace
 
+// Loads this file's kernels onto the current device (see preload_kernels).
+int preload_blas(pbr_ctx* c) {
+  hipFuncAttributes a;
+  PBR_HIP(c, hipFuncGetAttributes(&a, reinterpret_cast<const void*>(dot_real_kernel)));
+  return ST_OK;
+}
+
 // ------------------------------ host wrappers ------------------------------
 
 #define LAUNCH(kern, grid, ...)                                                 \

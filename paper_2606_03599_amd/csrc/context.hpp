@@ -235,6 +235,25 @@ int launch_eig_grad(pbr_ctx* c, const Geo& g, int block, int nvec, const double*
 // streaming copy of `bytes` (a multiple of 16) on the context stream (probe.hip)
 int launch_copy_probe(pbr_ctx* c, const void* src, void* dst, long bytes);
 
+// One kernel of each source file queried on the calling thread, so that the
+// runtime loads every code object of the library onto the device there (at
+// pbr_create) rather than at a first launch, which several host threads may
+// issue at once (pbr_band_paths).
+int preload_stencil(pbr_ctx* c);
+int preload_fft(pbr_ctx* c);
+int preload_blas(pbr_ctx* c);
+int preload_layout(pbr_ctx* c);
+int preload_grad(pbr_ctx* c);
+int preload_probe(pbr_ctx* c);
+inline int preload_kernels(pbr_ctx* c) {
+  PBR_TRY(preload_stencil(c));
+  PBR_TRY(preload_fft(c));
+  PBR_TRY(preload_blas(c));
+  PBR_TRY(preload_layout(c));
+  PBR_TRY(preload_grad(c));
+  return preload_probe(c);
+}
+
 // solver drivers (solver.cpp)
 int ensure_work(pbr_ctx* c, int slot, int block);
 int pcg_solve(pbr_ctx* c, int block, const double kappa[3], double shift, const cplx* b, cplx* x,

@@ -1633,3 +1633,10 @@ int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift)
   PBR_TRY(run_lines(c, T0, blocked, nb, 0, +1, 2, io5, 1.0 / (double)N, cap, nullptr));
   return ST_OK;
 }
+
+// Loads this file's kernels onto the current device (see preload_kernels).
+int preload_fft(pbr_ctx* c) {
+  hipFuncAttributes a;
+  PBR_HIP(c, hipFuncGetAttributes(&a, reinterpret_cast<const void*>(table_kernel)));
+  return ST_OK;
+}

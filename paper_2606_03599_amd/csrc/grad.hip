@@ -98,6 +98,13 @@ __global__ void __launch_bounds__(256) grad_kernel(GradArgs A) {
 
 }  // namespace
 
+// Loads this file's kernels onto the current device (see preload_kernels).
+int preload_grad(pbr_ctx* c) {
+  hipFuncAttributes a;
+  PBR_HIP(c, hipFuncGetAttributes(&a, reinterpret_cast<const void*>(grad_kernel)));
+  return ST_OK;
+}
+
 int launch_eig_grad(pbr_ctx* c, const Geo& g, int block, int nvec, const double* lam,
                     const double* w, const cplx* v, double* gC, double* grho) {
   const long N = c->layout_nodes(block);

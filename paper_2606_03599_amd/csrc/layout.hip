@@ -127,6 +127,13 @@ long tile_len(int L1, int L2, int L3) {
 
 }  // namespace
 
+// Loads this file's kernels onto the current device (see preload_kernels).
+int preload_layout(pbr_ctx* c) {
+  hipFuncAttributes a;
+  PBR_HIP(c, hipFuncGetAttributes(&a, reinterpret_cast<const void*>(gather_kernel)));
+  return ST_OK;
+}
+
 int dev_alloc(pbr_ctx* c, void** p, size_t bytes) {
   if (*p) return ST_OK;
   hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 16);

@@ -36,6 +36,13 @@ __global__ void __launch_bounds__(PROBE_THREADS)
 
 }  // namespace
 
+// Loads this file's kernels onto the current device (see preload_kernels).
+int preload_probe(pbr_ctx* c) {
+  hipFuncAttributes a;
+  PBR_HIP(c, hipFuncGetAttributes(&a, reinterpret_cast<const void*>(copy_probe_kernel)));
+  return ST_OK;
+}
+
 int launch_copy_probe(pbr_ctx* c, const void* src, void* dst, long bytes) {
   const long n = bytes / 16;
   if (n <= 0) return ST_OK;

@@ -636,6 +636,13 @@ constexpr int pal_lds_bytes(int npal) { return npal * 11 * 16; }
 
 }  // namespace
 
+// Loads this file's kernels onto the current device (see preload_kernels).
+int preload_stencil(pbr_ctx* c) {
+  hipFuncAttributes a;
+  PBR_HIP(c, hipFuncGetAttributes(&a, reinterpret_cast<const void*>((apply_stream_kernel<16, 11, true>))));
+  return ST_OK;
+}
+
 // Work split of a launch: tile shape (16 x 13; for the palette form also
 // 16 x 11) and chunk length.  A tile shape fits one work-group per CU (two for
 // the palette form's 16 x 11 tile when its palette is small), so a launch runs

@@ -159,6 +159,42 @@ def test_eigs_n16_blocks_vs_arpack_golden():
     ctx.close()
 
 
+@pytest.fixture(scope="module")
+def n32():
+    g = _gold("two_phase_n32.json")
+    dims = tuple(g["dims"])
+    C21, rho, _ = two_phase_cell(dims, radius=g["radius"], seed=g["seed"])
+    ctx = make_ctx(dims, C21, rho)
+    yield g, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("point", ["k", "gamma"])
+def test_eigs_n32_vs_sparse_oracle(n32, point):
+    """n = 32 heterogeneous cell (24,576 unknowns per block) against the
+    oracle's sparse shift-invert spectra (tests/golden, Sec. 6.1, Corollary
+    4.2): each block's 10 lowest, the merged 20 lowest and the full-space 20
+    lowest (the union of the block spectra), non-zero values at Gamma."""
+    g, ctx = n32
+    pt = g["points"][point]
+    kap = pt["kappa"]
+    nz = 3 if point == "gamma" else 0
+    for b in range(4):
+        log(f"eigs n=32 {point} block {b}")
+        ev, st, _ = ctx.eigs(kap, b, 10)
+        ref = np.array(pt["block_lowest"][b])
+        assert np.all(np.abs(ev - ref) <= TOL * np.abs(ref)), (b, ev, ref)
+        assert st.n_zero == nz
+    ref = np.array(pt["merged_lowest"])
+    log(f"eigs_merged n=32 {point}")
+    ev, st = ctx.eigs_merged(kap, 20)
+    assert np.all(np.abs(ev - ref) <= TOL * np.abs(ref)), (ev, ref)
+    log(f"eigs full space n=32 {point}")
+    ev, st, _ = ctx.eigs(kap, -1, 20)
+    assert np.all(np.abs(ev - ref) <= TOL * np.abs(ref)), (ev, ref)
+    assert st.n_zero == 4 * nz
+
+
 def test_error_paths():
     dims = (3, 4, 4)
     ctx = pbr.Context(dims)

@@ -44,3 +44,19 @@ def test_n16_golden_one_block_dense():
     C21, rho, _ = two_phase_cell(dims, radius=g["radius"], seed=g["seed"])
     ev = E.block_spectrum(dims, g["kappa"], C21, rho, 2)[:10]
     assert np.allclose(ev, g["block_lowest"][2], rtol=1e-10, atol=0)
+
+
+def test_n32_golden_structure():
+    """The n=32 file: per-block values ascending and positive (non-zero ones at
+    Gamma), the merged list the lowest 20 of their union, and every block's
+    10th value at or above the merged 20th (the certification of the cut)."""
+    g = _load("two_phase_n32.json")
+    assert tuple(g["dims"]) == (32, 32, 32)
+    for pt in g["points"].values():
+        blocks = [np.array(b) for b in pt["block_lowest"]]
+        merged = np.array(pt["merged_lowest"])
+        for b in blocks:
+            assert b.size == 10 and np.all(np.diff(b) >= 0) and b[0] > 1e-3
+        union = np.sort(np.concatenate(blocks))[:20]
+        assert np.array_equal(union, merged)
+        assert all(b[-1] >= merged[-1] for b in blocks)
