@@ -91,6 +91,9 @@ def parse():
     p.add_argument("--material-form", choices=("auto", "dense"), default="auto",
                    help="auto: the kernels read the material's palette form when it has one "
                         "(at most 256 distinct rows); dense: always the 21 + 1 doubles per node")
+    p.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="write the matvec traffic records under profiles/ from two rocprofv3 "
+                        "--pmc runs (FETCH_SIZE, WRITE_SIZE) of --matvec-only")
     p.add_argument("--serial-blocks", action="store_true",
                    help="solve the four blocks one after another instead of in lockstep")
     return p.parse_args()
@@ -230,6 +233,85 @@ def traffic_record(kernel_src, name):
     if rec.get("source_sha256") != h:
         return None
     return rec
+
+
+def traffic_records(fetch_dir, write_dir, n=128):
+    """Write profiles/matvec_blocks_n<n>_<form>_traffic.json from two rocprofv3
+    --pmc runs of `bench.py --matvec-only` (FETCH_SIZE, then WRITE_SIZE; KiB
+    per dispatch).  Each counter is scaled by the factor that makes it read
+    the true bytes of the copy probe's 2 GiB dispatches in the same run; the
+    four-block launches of each material form are the most frequent grid of
+    that form's kernel instance."""
+    import collections
+    import csv
+    import glob
+    import hashlib
+    import statistics
+
+    def load(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        per = collections.defaultdict(dict)
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = r["Dispatch_Id"]
+            per[key]["name"] = r["Kernel_Name"]
+            per[key]["grid"] = int(r.get("Grid_Size", 0) or 0)
+            per[key]["v"] = per[key].get("v", 0.0) + float(r["Counter_Value"])
+        return list(per.values())
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_bytes = (2 << 30)
+    cf = [d["v"] for d in fetch if "copy_probe_kernel" in d["name"]]
+    cw = [d["v"] for d in write if "copy_probe_kernel" in d["name"]]
+    f_factor = copy_bytes / 1024 / statistics.median(cf)
+    w_factor = copy_bytes / 1024 / statistics.median(cw)
+    src = os.path.join(ROOT, "paper_2606_03599_amd", "csrc", "stencil.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    nb4 = 4 * n ** 3 // 4
+    out = {}
+    for form, tag, bpn in (("dense", "false>", BYTES_PER_NODE), ("palette", "true>", PAL_BYTES_PER_NODE)):
+        fk = [d for d in fetch if "apply_stream_kernel" in d["name"] and d["name"].split("(")[0].rstrip().endswith(tag)]
+        wk = [d for d in write if "apply_stream_kernel" in d["name"] and d["name"].split("(")[0].rstrip().endswith(tag)]
+        if not fk or not wk:
+            continue
+        grid = collections.Counter(d["grid"] for d in fk).most_common(1)[0][0]
+        fv = [d["v"] for d in fk if d["grid"] == grid]
+        wv = [d["v"] for d in wk if d["grid"] == grid]
+        fb = statistics.mean(fv) * 1024 * f_factor
+        wb = statistics.mean(wv) * 1024 * w_factor
+        rec = {
+            "kernel": f"apply_stream_kernel, {form} material form: fused (A + delta M) x of the "
+                      f"four parity blocks in one launch, n={n} (4 x {n ** 3 // 4} nodes)",
+            "source": "paper_2606_03599_amd/csrc/stencil.hip", "source_sha256": sha,
+            "commands": [
+                "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 200 rocprofv3 --pmc FETCH_SIZE "
+                "--output-format csv -d $R/gpurun_out/pf -o pf -- python3 -u $R/bench.py "
+                "--matvec-only --mv-iters 20",
+                "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 200 rocprofv3 --pmc WRITE_SIZE "
+                "--output-format csv -d $R/gpurun_out/pw -o pw -- python3 -u $R/bench.py "
+                "--matvec-only --mv-iters 20",
+                "python3 $R/bench.py --traffic-record $R/gpurun_out/pf $R/gpurun_out/pw"],
+            "grid_threads": grid, "launches_averaged": len(fv),
+            "fetch_size_kib_raw": round(statistics.mean(fv), 2),
+            "write_size_kib_raw": round(statistics.mean(wv), 2),
+            "copy_calibration": {
+                "kernel": "copy_probe_kernel (pbr_copy_probe of 2 GiB, same runs)",
+                "true_kib_each_way": copy_bytes / 1024,
+                "fetch_size_kib": round(statistics.median(cf), 2),
+                "write_size_kib": round(statistics.median(cw), 2),
+                "fetch_factor": round(f_factor, 5), "write_factor": round(w_factor, 5)},
+            "algorithmic_bytes_per_node": bpn,
+            "hbm_fetch_bytes_per_launch": int(fb), "hbm_write_bytes_per_launch": int(wb),
+            "hbm_bytes_per_launch": int(fb + wb),
+            "algorithmic_bytes_per_launch": bpn * nb4,
+            "traffic_over_algorithmic": round((fb + wb) / (bpn * nb4), 3)}
+        path = os.path.join(ROOT, "profiles", f"matvec_blocks_n{n}_{form}_traffic.json")
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        out[form] = rec["traffic_over_algorithmic"]
+    return out
 
 
 def refinement_study(grids=(16, 32, 64, 128), ref=256, nev=8, points=("X", "W", "L")):
@@ -377,6 +459,9 @@ def main():
         print(json.dumps({"error": "this build measures one GPU: collectives and sharding are "
                                    "not part of it, so --gpus must be 1"}))
         sys.exit(2)
+    if args.traffic_record:
+        print(json.dumps(traffic_records(*args.traffic_record)), flush=True)
+        return
     if args.study == "refinement":
         print(json.dumps(refinement_study()), flush=True)
         return

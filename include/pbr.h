@@ -263,7 +263,7 @@ pbr_status pbr_eigs(pbr_ctx *c, const double kappa[3], int block, int nev,
 
 /* nev lowest eigenvalues of the full pencil obtained by solving the four parity
  * blocks and merging their spectra (Sec. 6.1).  Each block starts with
- * nev_b = ceil(nev/4) + 4 eigenpairs; a block whose largest computed eigenvalue
+ * nev_b = ceil(nev/4) + 1 eigenpairs; a block whose largest computed eigenvalue
  * lies below the merged nev-th value is recomputed with more eigenpairs until
  * every block certifies the cut (at most 8 rounds); PBR_ENOCONV, with the
  * merged values written, when a block stays uncertified.  Needs an even grid. */

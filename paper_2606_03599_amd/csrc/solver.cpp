@@ -846,7 +846,9 @@ void add_stats(pbr_stats* acc, const pbr_stats& one) {
 }  // namespace
 
 // Lowest nev eigenvalues of the full pencil at each of nk wave vectors from the
-// four blocks (Corollary 4.2): each block is asked for nev/4 + 4 values; a block
+// four blocks (Corollary 4.2): each block is asked for ceil(nev/4) + 1 values
+// (the full spectrum's near-fourfold clusters put one member in each block, so a
+// block rarely holds more than ceil(nev/4) of the lowest nev); a block
 // whose largest computed value lies below the merged nev-th value may hide
 // smaller ones that were not computed, so it is solved again with more values
 // until no block is flagged.  Up to PBR_KSLOTS k-points are solved at once, all
@@ -880,7 +882,7 @@ int merged_path(pbr_ctx* c, int nk, const double* kappas, int nev, double shift,
       const double* kap = kappas + 3 * (k0 + q);
       const int nz = is_gamma(kap) ? 3 : 0;
       for (int b = 0; b < 4; ++b)
-        nev_b[q][b] = (int)std::min<long>((nev + 3) / 4 + 4, dimb - nz - 1);
+        nev_b[q][b] = (int)std::min<long>((nev + 3) / 4 + 1, dimb - nz - 1);
       need[q] = 0xF;
     }
     for (int round = 0; round < 8; ++round) {
