@@ -86,7 +86,8 @@ def parse():
                    help="compare with the full space on every k-th path point (0: skip)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     p.add_argument("--matvec-only", action="store_true",
-                   help="only the matvec timing (for hardware-counter runs)")
+                   help="only the four-block matvec launches (dense and palette form) and the "
+                        "copy probe, timed (for kernel-trace and hardware-counter runs)")
     p.add_argument("--mv-iters", type=int, default=100)
     p.add_argument("--material-form", choices=("auto", "dense"), default="auto",
                    help="auto: the kernels read the material's palette form when it has one "
@@ -271,9 +272,16 @@ def traffic_records(fetch_dir, write_dir, n=128):
         sha = hashlib.sha256(f.read()).hexdigest()
     nb4 = 4 * n ** 3 // 4
     out = {}
-    for form, tag, bpn in (("dense", "false>", BYTES_PER_NODE), ("palette", "true>", PAL_BYTES_PER_NODE)):
-        fk = [d for d in fetch if "apply_stream_kernel" in d["name"] and d["name"].split("(")[0].rstrip().endswith(tag)]
-        wk = [d for d in write if "apply_stream_kernel" in d["name"] and d["name"].split("(")[0].rstrip().endswith(tag)]
+    import re
+    inst = re.compile(r"apply_stream_kernel<\s*\d+,\s*\d+,\s*(true|false)\s*>")
+
+    def form_of(name):
+        m = inst.search(name)
+        return None if m is None else ("palette" if m.group(1) == "true" else "dense")
+
+    for form, bpn in (("dense", BYTES_PER_NODE), ("palette", PAL_BYTES_PER_NODE)):
+        fk = [d for d in fetch if form_of(d["name"]) == form]
+        wk = [d for d in write if form_of(d["name"]) == form]
         if not fk or not wk:
             continue
         grid = collections.Counter(d["grid"] for d in fk).most_common(1)[0][0]
@@ -518,11 +526,14 @@ def main():
         ctx.set_palette(True)
         t_b4_pal = blocks_timing(torch, ctx, n, kap_mv, delta, max(10, args.mv_iters // 2))
     ctx.set_palette(form == "palette")
-    t_blk = kernel_timing(torch, ctx, n, kap_mv, delta, args.mv_iters, (0, 1, 2, 3), "apply")
-    t_full = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 4), (-1,),
-                           "apply")
-    t_pc = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 2), (0, 1, 2, 3),
-                         "precond")
+    if args.matvec_only:  # counter runs: the four-block launches and the copy probe only
+        t_blk = t_full = t_pc = float("nan")
+    else:
+        t_blk = kernel_timing(torch, ctx, n, kap_mv, delta, args.mv_iters, (0, 1, 2, 3), "apply")
+        t_full = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 4), (-1,),
+                               "apply")
+        t_pc = kernel_timing(torch, ctx, n, kap_mv, delta, max(8, args.mv_iters // 2),
+                             (0, 1, 2, 3), "precond")
     nb = n ** 3 // 4
     bpn = PAL_BYTES_PER_NODE if form == "palette" else BYTES_PER_NODE
     b4_bytes = BYTES_PER_NODE * 4 * nb

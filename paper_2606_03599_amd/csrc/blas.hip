@@ -287,6 +287,72 @@ __global__ void combine_kernel(long n, int m, int k, const cplx* __restrict__ U,
   }
 }
 
+// The same product on the FP64 matrix cores (v_mfma_f64_16x16x4_f64).  In real
+// arithmetic, with complex entries as (re, im) pairs, V_r = U_r Y_r where each
+// complex y of Y becomes the 2 x 2 block [[re y, im y], [-im y, re y]]; the
+// kernel computes its transpose V_r^T = Y_r^T U_r^T, so that the 16 output rows
+// t of one tile sit on 16 consecutive lanes.  Operand and result lanes of the
+// instruction: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, and lane
+// l's result slot r holds D[4 r + l / 16][l % 16].  A wave owns 16 rows t and
+// up to MM_TILES x 16 real output columns (MM_TILES x 8 complex ones); the
+// work-group stages Y_r^T of its column chunk in LDS.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int MM_TILES = 4;            // 16-column output tiles per wave
+constexpr int MM_COLS = MM_TILES * 8;  // complex output columns per chunk
+constexpr int MM_MAXM = 90;            // basis columns (K = 2 m real) at most
+
+__global__ void __launch_bounds__(RT) combine_mfma_kernel(long n, int m, int k, int c0,
+                                                         const cplx* __restrict__ U, long ld,
+                                                         const cplx* __restrict__ Y,
+                                                         cplx* __restrict__ V, long ldv) {
+  // Y_r^T of output columns [c0, c0 + MM_COLS): yt[kr * (16 MM_TILES) + col],
+  // kr < 2 m rounded up to a multiple of 4 (dynamic LDS of that size)
+  extern __shared__ double yt[];
+  const int kr_n = 2 * m + ((2 * m) & 2);  // K padded to a multiple of 4
+  const int nc = min(MM_COLS, k - c0);
+  for (int e = threadIdx.x; e < kr_n * 16 * MM_TILES; e += blockDim.x) {
+    const int kr = e / (16 * MM_TILES), col = e % (16 * MM_TILES);
+    const int j = kr >> 1, s_ = kr & 1, c = col >> 1, q = col & 1;
+    double v = 0.0;
+    if (j < m && c < nc) {
+      const cplx y = Y[(long)(c0 + c) * m + j];
+      v = s_ == 0 ? (q == 0 ? y.x : y.y) : (q == 0 ? -y.y : y.x);
+    }
+    yt[e] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long t0 = ((long)blockIdx.x * (RT / 64) + wave) * 16;
+  if (t0 >= n) return;
+  const long t = t0 + (lane & 15);
+  const int kl = lane >> 4;
+  v4d acc[MM_TILES];
+#pragma unroll
+  for (int a = 0; a < MM_TILES; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < kr_n; kk += 4) {
+    const int kr = kk + kl, j = kr >> 1;
+    double b = 0.0;
+    if (t < n && j < m) {
+      const cplx u = U[(long)j * ld + t];
+      b = (kr & 1) ? u.y : u.x;
+    }
+#pragma unroll
+    for (int a = 0; a < MM_TILES; ++a) {
+      const double av = yt[kr * (16 * MM_TILES) + a * 16 + (lane & 15)];
+      acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[a], 0, 0, 0);
+    }
+  }
+  // lane l slot r: real output column a*16 + 4 r + l/16, row t0 + l%16
+  double* Vd = reinterpret_cast<double*>(V);
+#pragma unroll
+  for (int a = 0; a < MM_TILES; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int col = a * 16 + 4 * r + kl, c = col >> 1, q = col & 1;
+      if (c < nc && t < n) Vd[2 * ((long)(c0 + c) * ldv + t) + q] = acc[a][r];
+    }
+}
+
 // Deterministic pseudo-random start vector (splitmix64 hash of seed and index).
 __device__ inline unsigned long long splitmix(unsigned long long z) {
   z += 0x9E3779B97F4A7C15ull;
@@ -439,7 +505,18 @@ int gemv_sub(pbr_ctx* c, hipStream_t st_, long n, int m, const cplx* U, long ld,
 
 int combine(pbr_ctx* c, hipStream_t st_, long n, int m, int k, const cplx* U, long ld, const cplx* Y, cplx* V,
             long ldv) {
-  LAUNCH(combine_kernel, grid_for(n), n, m, k, U, ld, Y, V, ldv);
+  if (m > MM_MAXM) {
+    LAUNCH(combine_kernel, grid_for(n), n, m, k, U, ld, Y, V, ldv);
+    return ST_OK;
+  }
+  // matrix cores: one launch per chunk of MM_COLS output columns
+  const unsigned g = ceil_div(n, 16 * (RT / 64));
+  const size_t lds = sizeof(double) * (2 * m + ((2 * m) & 2)) * 16 * MM_TILES;
+  for (int c0 = 0; c0 < k; c0 += MM_COLS) {
+    hipLaunchKernelGGL(combine_mfma_kernel, dim3(g), dim3(RT), lds, st_, n, m, k, c0, U, ld, Y, V,
+                       ldv);
+    PBR_HIP(c, hipGetLastError());
+  }
   return ST_OK;
 }
 
