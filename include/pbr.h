@@ -229,8 +229,9 @@ pbr_status pbr_precond(pbr_ctx *c, const double kappa[3], int block, double shif
  * and result as pbr_precond with on_device = 1 (bit for bit); r and z are device
  * memory on the context's device, work is ordered on the context's stream.
  * The per-wave-vector tables the kernels read (roots, twists, mode phases of the
- * three axes) are written by each call into a fixed array of 9 x 256 complex128
- * (36,864 bytes) that every device the library runs on holds until the process
+ * three axes, and for a block the mode phases in the order of its three-pass
+ * transforms) are written by each call into a fixed array of 12 x 256 complex128
+ * (49,152 bytes) that every device the library runs on holds until the process
  * ends, set up by pbr_create; hence every n_l must be at most 256 (PBR_EINVAL
  * otherwise, before any work).  The array is shared by all contexts on a device
  * and keeps the last call's contents: calls that overlap in time on one device
