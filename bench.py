@@ -453,9 +453,9 @@ def gap_gradient_study(n, nev, points=("X", "R"), seed=0):
 def cells_study(nk, nev, count=8, seed=0):
     """Uneven batch of two-phase cells (n drawn from {64, 96, 128}, inclusion
     radius from U[0.2, 0.4], each with its own seeded inclusion stiffness): the
-    blocked band paths of all cells one after another, then all cells at once
-    (pbr_band_paths: one host thread and stream per cell).  Results must agree
-    bit for bit."""
+    blocked band paths of all cells, group of 4 path points by group, first one
+    cell after another, then all cells at once (pbr_band_paths: one host thread
+    and stream per cell).  Results must agree bit for bit."""
     import numpy as np
     import torch
     from paper_2606_03599_amd import pbr
@@ -471,27 +471,33 @@ def cells_study(nk, nev, count=8, seed=0):
     radii = [round(c[1], 4) for c in cells]
     del cells
     log(f"cells: n = {sizes}, radius = {radii}, {nk} k-points, nev = {nev}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    serial = []
-    for q, ctx in enumerate(ctxs):
-        serial.append(ctx.band_path(kappas, nev)[0])
-        log(f"cell {q} (n={sizes[q]}) one after another: {time.perf_counter() - t0:.1f} s")
-    t_serial = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    conc, sts = pbr.band_paths(ctxs, [kappas] * len(ctxs), nev)
-    t_conc = time.perf_counter() - t0
-    log(f"all cells at once: {t_conc:.1f} s (one after another {t_serial:.1f} s)")
-    same = all(np.array_equal(a, b) for a, b in zip(serial, conc))
+    t_serial = t_conc = 0.0
+    same = True
+    solves = 0
+    for g0 in range(0, nk, 4):
+        ks = kappas[g0:g0 + 4]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        serial = [ctx.band_path(ks, nev)[0] for ctx in ctxs]
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        conc, sts = pbr.band_paths(ctxs, [ks] * len(ctxs), nev)
+        tc = time.perf_counter() - t0
+        t_serial += ts
+        t_conc += tc
+        solves += int(sum(st.op_applies for st in sts))
+        same = same and all(np.array_equal(a, b) for a, b in zip(serial, conc))
+        log(f"points {g0}-{g0 + len(ks) - 1}: one after another {ts:.1f} s, all at once {tc:.1f} s "
+            f"(totals {t_serial:.1f} / {t_conc:.1f} s), identical {same}")
     for ctx in ctxs:
         ctx.close()
     return {"study": "uneven batch of cells, blocked band paths, one after another vs all cells "
-                     "at once (pbr_band_paths)",
+                     "at once (pbr_band_paths), 4 path points at a time",
             "cells": [{"n": n, "radius": r} for n, r in zip(sizes, radii)],
             "k_points": nk, "nev": nev,
             "one_after_another_s": round(t_serial, 3), "concurrent_s": round(t_conc, 3),
-            "speedup": round(t_serial / t_conc, 3),
-            "solves": int(sum(s.op_applies for s in sts)),
+            "speedup": round(t_serial / t_conc, 3), "solves": solves,
             "results_identical": bool(same)}
 
 
@@ -512,7 +518,7 @@ def main():
                                             args.nev if args.nev > 0 else 30)), flush=True)
         return
     if args.study == "cells":
-        print(json.dumps(cells_study(args.nk if args.nk != 16 else 6,
+        print(json.dumps(cells_study(args.nk if args.nk != 16 else 24,
                                      args.nev if args.nev > 0 else 16)), flush=True)
         return
     import numpy as np

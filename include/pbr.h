@@ -236,7 +236,10 @@ pbr_status pbr_precond(pbr_ctx *c, const double kappa[3], int block, double shif
  * otherwise, before any work).  The array is shared by all contexts on a device
  * and keeps the last call's contents: calls that overlap in time on one device
  * (other streams, other host threads) race on it and must be serialised by the
- * caller.  PBR_ESTATE before pbr_set_material. */
+ * caller.  Where pbr_precond tunes a kernel's work split at its first call on a
+ * box, this call uses the split the context has tuned, or the default one, and
+ * matches pbr_precond bit for bit once pbr_precond has run on that box.
+ * PBR_ESTATE before pbr_set_material. */
 pbr_status pbr_precond_noalloc(pbr_ctx *c, const double kappa[3], int block, double shift,
                                const void *r, void *z);
 

@@ -97,6 +97,11 @@ struct pbr_ctx {
     int ti = 0, tj = 0, chunk = 0;
   } stencil_tune[PBR_TUNE_SLOTS];
   int stencil_tune_next = 0;
+  // i-width of the block mode-solve pass chosen per (batch size, box)
+  struct SolveTune {
+    int nb = 0, L1 = 0, L2 = 0, L3 = 0, bi = 0;
+  } solve_tune[PBR_TUNE_SLOTS];
+  int solve_tune_next = 0;
   int pin_ti = 0, pin_tj = 0;  // stencil tile shape pinned by pbr_set_stencil_shape (0: tuned)
   int precond_passes = 0;      // pbr_set_precond_passes: 0 automatic, 3 or 5
   hipStream_t stream = nullptr;

@@ -975,10 +975,9 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
 // symbols, unfolds, transforms back and writes in place.  Also finishes |r|^2 and the convergence test (rr_in) and
 // writes the (r, z) partials, like fft_solve_kernel.
 constexpr int SOLVE_THREADS = 512;
-// i-values per work-group (at most) for third axes longer than 32: 16 (50 KB of
-// LDS, three work-groups per CU) measured 4 % faster on the path at n = 128
-// than 32 (100 KB, one per CU)
-constexpr int SOLVE_BIM = 16;
+// (i-values per work-group: 16 or 32 by the LDS the instance holds, bi <= that
+// at run time; tuned_solve_width picks it.  At n = 128 on the path 16 (50 KB of
+// LDS, three work-groups per CU) measured 4 % faster than 32 (100 KB, one per CU).)
 
 template <int L3T, int BIM>
 __global__ void __launch_bounds__(SOLVE_THREADS) solve_plane_kernel(SolveArgs S, int bi) {
@@ -1366,6 +1365,105 @@ struct SolveIO {
   int init = 0;
 };
 
+typedef void (*PlaneSolveKernel)(SolveArgs, int);
+
+// Mode-solve kernel of the three-pass structure for third-axis length L3 and
+// i-width bi: the instance whose LDS holds bi (16 or 32 i-values).
+PlaneSolveKernel solve_plane_for(int L3, int bi) {
+  switch (L3) {
+#define PBR_CASE(n)                                                           \
+  case n:                                                                     \
+    return bi <= 16 ? solve_plane_kernel<n, 16> : solve_plane_kernel<n, 32>;
+    PBR_PLANE_LENGTHS(PBR_CASE)
+#undef PBR_CASE
+    default:
+      return nullptr;
+  }
+}
+
+// i-width of the mode-solve pass for this box and batch size: the cost model's
+// choice (16, or the largest power of two <= 16 dividing n1; at most 32 for
+// third axes up to 32) unless another candidate (8, 16, 32 dividing n1) is at
+// least 5 % faster when timed on a copy of the batch's data at the first call
+// (the pass works in place; the copy is refreshed before each timed launch).
+// The choice is kept per context, so later launches, and the graphs that
+// capture them, use it; with a 5 % margin it is the same from run to run.
+int tuned_solve_width(pbr_ctx* c, const SolveArgs& S, int nb, bool may_tune, int* bi_out) {
+  for (const auto& e : c->solve_tune)
+    if (e.nb == nb && e.L1 == S.L1 && e.L2 == S.L2 && e.L3 == S.L3 && e.bi > 0) {
+      *bi_out = e.bi;
+      return ST_OK;
+    }
+  auto fits = [&](int bi) { return bi >= 2 && S.L1 % bi == 0; };
+  int model = S.L3 > 32 ? 16 : 32;
+  while (model > 2 && !fits(model)) model >>= 1;
+  int cand[3], ncand = 0;
+  cand[ncand++] = model;
+  for (int bi : {8, 16, 32})
+    if (bi != model && fits(bi)) cand[ncand++] = bi;
+  *bi_out = model;
+  if (!may_tune) return ST_OK;  // no timing, no allocation, nothing recorded
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  const bool capturing =
+      hipStreamIsCapturing(c->stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
+  const long n3 = 3 * S.N;
+  cplx* scratch = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!capturing && ncand > 1 && S.N >= 4096 &&
+      dev_alloc(c, (void**)&scratch, sizeof(cplx) * n3 * nb) == ST_OK &&
+      hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    SolveArgs T = S;
+    for (int t = 0; t < nb; ++t) {
+      T.b[t].data = scratch + (long)t * n3;
+      T.b[t].st = nullptr;
+      T.b[t].part_out = nullptr;
+      T.b[t].rr_in = nullptr;
+    }
+    float best_ms = -1.0f;
+    bool ok = true;
+    for (int r = 0; r < 2 && ok; ++r)  // the first round warms the caches
+      for (int k = 0; k < ncand && ok; ++k) {
+        float tot = 0.0f;
+        for (int rep = 0; ok && rep < (r == 1 ? 3 : 1); ++rep) {
+          for (int t = 0; t < nb && ok; ++t)
+            ok = hipMemcpyAsync(T.b[t].data, S.b[t].data, sizeof(cplx) * n3,
+                                hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+          const long nwg = (long)(S.L1 / cand[k]) * S.L2;
+          ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
+          if (ok)
+            hipLaunchKernelGGL(solve_plane_for(S.L3, cand[k]), dim3((unsigned)(nwg * nb)),
+                               dim3(SOLVE_THREADS), 0, c->stream, T, cand[k]);
+          ok = ok && hipGetLastError() == hipSuccess &&
+               hipEventRecord(e1, c->stream) == hipSuccess &&
+               hipEventSynchronize(e1) == hipSuccess;
+          float ms = 0.0f;
+          ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+          tot += ms;
+        }
+        if (ok && r == 1 && (best_ms < 0.0f || tot < 0.95f * best_ms)) {
+          best_ms = tot;
+          *bi_out = cand[k];
+        }
+      }
+    if (!ok) *bi_out = model;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (scratch) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(scratch);
+  }
+  if (capturing) return ST_OK;  // not recorded: the next eager call tunes
+  auto& slot = c->solve_tune[c->solve_tune_next];
+  c->solve_tune_next = (c->solve_tune_next + 1) % PBR_TUNE_SLOTS;
+  slot.nb = nb;
+  slot.L1 = S.L1;
+  slot.L2 = S.L2;
+  slot.L3 = S.L3;
+  slot.bi = *bi_out;
+  return ST_OK;
+}
+
 void fill_symbol_args(const pbr_ctx* c, double shift, SolveArgs& S) {
   for (int m = 0; m < 3; ++m)
     for (int d = 0; d < 5; ++d) S.cf[m][d] = c->cf[m][d];
@@ -1374,7 +1472,7 @@ void fill_symbol_args(const pbr_ctx* c, double shift, SolveArgs& S) {
 }
 
 int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift, long part_cap,
-              int* nparts) {
+              int* nparts, bool may_tune = true) {
   const FftTables& T = *io[0].T;
   SolveArgs S;
   S.L1 = c->n1;
@@ -1399,23 +1497,12 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
     S.b[t].init = io[t].init;
   }
   if (io[0].perm) {
-    // three-pass structure: every axis in digit-reversed mode order
-    typedef void (*PlaneSolveKernel)(SolveArgs, int);
-    PlaneSolveKernel k = nullptr;
-    switch (S.L3) {
-#define PBR_CASE(n)                                        \
-  case n:                                                  \
-    k = solve_plane_kernel<n, (n > 32 ? SOLVE_BIM : 32)>; \
-    break;
-      PBR_PLANE_LENGTHS(PBR_CASE)
-#undef PBR_CASE
-      default:
-        break;
-    }
-    const int bim = S.L3 > 32 ? SOLVE_BIM : 32;
-    int bi = bim;
-    while (bi > 2 && S.L1 % bi) bi >>= 1;
-    if (!k || S.L1 % bi) {
+    // three-pass structure: every axis in digit-reversed mode order; the
+    // i-width of a work-group is tuned per (box, batch size)
+    int bi = 0;
+    PBR_TRY(tuned_solve_width(c, S, nb, may_tune, &bi));
+    const PlaneSolveKernel k = solve_plane_for(S.L3, bi);
+    if (!k) {
       c->set_error("no mode-solve pass for this block box");
       return ST_EINVAL;
     }
@@ -1454,7 +1541,7 @@ namespace {
 // The passes of the preconditioner of one layout with the tables T: three for
 // a block with a plane pass (T then holds the permuted mode phases), else five.
 int precond_passes(pbr_ctx* c, const FftTables& T, int block, double shift, const cplx* r,
-                   cplx* z) {
+                   cplx* z, bool may_tune) {
   const bool blocked = block >= 0;
   const long N = c->layout_nodes(block);
   if (blocked && plane_pass(c)) {
@@ -1462,7 +1549,7 @@ int precond_passes(pbr_ctx* c, const FftTables& T, int block, double shift, cons
     SolveIO s{block, z, nullptr, nullptr, &T};
     s.perm = true;
     PBR_TRY(run_plane(c, 1, -1, 0, &f, 1.0, 0, nullptr));
-    PBR_TRY(run_solve(c, true, 1, &s, shift, 0, nullptr));
+    PBR_TRY(run_solve(c, true, 1, &s, shift, 0, nullptr, may_tune));
     PBR_TRY(run_plane(c, 1, +1, 0, &v, 1.0 / (double)N, 0, nullptr));
     return ST_OK;
   }
@@ -1518,7 +1605,7 @@ int launch_precond(pbr_ctx* c, const double kappa[3], int block, double shift, c
                    cplx* z) {
   const bool blocked = block >= 0;
   PBR_TRY(ensure_tables(c, 0, blocked, kappa));
-  return precond_passes(c, c->tables(0, blocked), block, shift, r, z);
+  return precond_passes(c, c->tables(0, blocked), block, shift, r, z, true);
 }
 
 int launch_precond_noalloc(pbr_ctx* c, const double kappa[3], int block, double shift,
@@ -1558,7 +1645,7 @@ int launch_precond_noalloc(pbr_ctx* c, const double kappa[3], int block, double 
     }
   }
   PBR_HIP(c, hipGetLastError());
-  return precond_passes(c, T, block, shift, r, z);
+  return precond_passes(c, T, block, shift, r, z, false);
 }
 
 int launch_pcg_precond_batch(pbr_ctx* c, int nb, const PcgStep* P, double shift) {
