@@ -450,7 +450,7 @@ def gap_gradient_study(n, nev, points=("X", "R"), seed=0):
                                   "rel_diff": abs(ana - fd) / max(abs(fd), 1e-300)}}
 
 
-def cells_study(nk, nev, count=8, seed=0):
+def cells_study(nk, nev, count=8, seed=0, first=0):
     """Uneven batch of two-phase cells (n drawn from {64, 96, 128}, inclusion
     radius from U[0.2, 0.4], each with its own seeded inclusion stiffness): the
     blocked band paths of all cells, group of 4 path points by group, first one
@@ -462,6 +462,8 @@ def cells_study(nk, nev, count=8, seed=0):
     from synth import batch_cells, sc_path
     cells = batch_cells(count, seed=seed)
     kappas, _ = sc_path(nk)
+    if first > 0:
+        kappas = kappas[:first]
     ctxs = []
     for n, r, C21, rho in cells:
         ctx = pbr.Context((n, n, n))
@@ -473,8 +475,9 @@ def cells_study(nk, nev, count=8, seed=0):
     log(f"cells: n = {sizes}, radius = {radii}, {nk} k-points, nev = {nev}")
     t_serial = t_conc = 0.0
     same = True
+    max_diff = 0.0
     solves = 0
-    for g0 in range(0, nk, 4):
+    for g0 in range(0, len(kappas), 4):
         ks = kappas[g0:g0 + 4]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -488,17 +491,20 @@ def cells_study(nk, nev, count=8, seed=0):
         t_conc += tc
         solves += int(sum(st.op_applies for st in sts))
         same = same and all(np.array_equal(a, b) for a, b in zip(serial, conc))
+        diff = [float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(serial, conc)]
+        max_diff = max(max_diff, max(diff))
         log(f"points {g0}-{g0 + len(ks) - 1}: one after another {ts:.1f} s, all at once {tc:.1f} s "
-            f"(totals {t_serial:.1f} / {t_conc:.1f} s), identical {same}")
+            f"(totals {t_serial:.1f} / {t_conc:.1f} s), identical {same}, max rel diff per cell "
+            + " ".join(f"{d:.1e}" for d in diff))
     for ctx in ctxs:
         ctx.close()
     return {"study": "uneven batch of cells, blocked band paths, one after another vs all cells "
                      "at once (pbr_band_paths), 4 path points at a time",
             "cells": [{"n": n, "radius": r} for n, r in zip(sizes, radii)],
-            "k_points": nk, "nev": nev,
+            "k_points": len(kappas), "nev": nev,
             "one_after_another_s": round(t_serial, 3), "concurrent_s": round(t_conc, 3),
             "speedup": round(t_serial / t_conc, 3), "solves": solves,
-            "results_identical": bool(same)}
+            "results_identical": bool(same), "max_rel_diff": max_diff}
 
 
 def main():
@@ -519,7 +525,8 @@ def main():
         return
     if args.study == "cells":
         print(json.dumps(cells_study(args.nk if args.nk != 16 else 24,
-                                     args.nev if args.nev > 0 else 16)), flush=True)
+                                     args.nev if args.nev > 0 else 16, first=args.first)),
+              flush=True)
         return
     import numpy as np
     import torch

@@ -28,15 +28,41 @@ constexpr int NSTATE = 5 * PBR_KSLOTS;  // device CG scalar sets (one per work a
 
 int alloc_vec(pbr_ctx* c, cplx** p, long n3) { return dev_alloc(c, (void**)p, sizeof(cplx) * n3); }
 
+// Grows the Krylov bases to cols columns.  The Ritz vectors a finished run left
+// in U2 move to the new U2: a later run's warm start reads them (a block solved
+// again with more eigenpairs needs a larger basis and starts from its own
+// earlier Ritz vectors), and dropping them would make that start depend on
+// whether an earlier call had already grown the basis.
 int ensure_basis(pbr_ctx* c, LayoutWork& W, int cols) {
   if (W.ucols >= cols) return ST_OK;
+  cplx* old2 = W.U2;
+  const int keep = old2 ? std::min(W.ritz_n, W.ucols) : 0;
   dev_free(W.U);
-  dev_free(W.U2);
   W.U = W.U2 = nullptr;
   W.ucols = 0;
   W.ritz_n = 0;
-  PBR_TRY(alloc_vec(c, &W.U, 3 * W.N * (long)cols));
-  PBR_TRY(alloc_vec(c, &W.U2, 3 * W.N * (long)cols));
+  const long n3 = 3 * W.N;
+  int rc = alloc_vec(c, &W.U, n3 * (long)cols);
+  if (rc == ST_OK) rc = alloc_vec(c, &W.U2, n3 * (long)cols);
+  if (rc == ST_OK && keep > 0) {
+    hipError_t e = hipMemcpyAsync(W.U2, old2, sizeof(cplx) * n3 * keep, hipMemcpyDeviceToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      c->set_error(std::string("Ritz vector copy: ") + hipGetErrorString(e));
+      rc = ST_EDEVICE;
+    } else {
+      W.ritz_n = keep;
+    }
+  }
+  dev_free(old2);
+  if (rc != ST_OK) {
+    dev_free(W.U);
+    dev_free(W.U2);
+    W.U = W.U2 = nullptr;
+    W.ritz_n = 0;
+    return rc;
+  }
   W.ucols = cols;
   return ST_OK;
 }
