@@ -95,6 +95,9 @@ def parse():
     p.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="write the matvec traffic records under profiles/ from two rocprofv3 "
                         "--pmc runs (FETCH_SIZE, WRITE_SIZE) of --matvec-only")
+    p.add_argument("--kernel-stats", metavar="TRACE_DIR",
+                   help="print a markdown summary of a rocprofv3 --kernel-trace --stats "
+                        "--output-format csv directory: per kernel and per launch grid")
     p.add_argument("--serial-blocks", action="store_true",
                    help="solve the four blocks one after another instead of in lockstep")
     return p.parse_args()
@@ -218,6 +221,42 @@ def cpu_sample(n, kappa, C21_full, rho_full, delta, reps=3):
             t_pc.append(t2 - t1)
     assert np.isfinite(z).all()
     return float(np.median(t_mv)), float(np.median(t_pc)), dims
+
+
+def kernel_stats(trace_dir, top=16):
+    """Markdown summary of a rocprofv3 kernel trace (csv): calls, mean and total
+    time per kernel (its stats file), then mean time per (kernel, launch grid)
+    from the trace itself."""
+    import collections
+    import csv
+    import glob
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    trace = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not stats or not trace:
+        raise SystemExit(f"no kernel_stats.csv / kernel_trace.csv under {trace_dir}")
+
+    def short(name):
+        name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+        return name[:name.index(">") + 1] if "<" in name else name.split("(")[0]
+
+    rows = list(csv.DictReader(open(stats[0])))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["| kernel | calls | avg us | total s | % |", "|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e9:.3f} | {float(r['Percentage']):.1f} |")
+    out.append(f"\nTotal kernel time {total / 1e9:.3f} s.\n")
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in csv.DictReader(open(trace[0])):
+        key = (short(r["Kernel_Name"]), r["Grid_Size_X"], r["Grid_Size_Y"], r["Grid_Size_Z"],
+               r["Workgroup_Size_X"])
+        agg[key][0] += 1
+        agg[key][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    out += ["| kernel | grid (x, y, z) | work-group | launches | avg us |",
+            "|---|---|---|---|---|"]
+    for k, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        out.append(f"| {k[0]} | ({k[1]}, {k[2]}, {k[3]}) | {k[4]} | {c} | {t / c:.1f} |")
+    return "\n".join(out)
 
 
 def traffic_record(kernel_src, name):
@@ -513,6 +552,9 @@ def main():
         print(json.dumps({"error": "this build measures one GPU: collectives and sharding are "
                                    "not part of it, so --gpus must be 1"}))
         sys.exit(2)
+    if args.kernel_stats:
+        print(kernel_stats(args.kernel_stats), flush=True)
+        return
     if args.traffic_record:
         print(json.dumps(traffic_records(*args.traffic_record)), flush=True)
         return

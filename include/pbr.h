@@ -177,6 +177,16 @@ pbr_status pbr_set_stencil_shape(pbr_ctx *c, int ti, int tj);
  * call.  PBR_EINVAL for a NULL context or another value. */
 pbr_status pbr_set_precond_passes(pbr_ctx *c, int passes);
 
+/* i-width of the mode-solve pass of the three-pass block preconditioner (the
+ * third-axis transforms and per-mode 3 x 3 solves of Sec. 5.3-5.4): bi
+ * consecutive i-values of both sub-lattices per work-group.  0 (the default)
+ * lets the autotuner choose per box and batch size (timed on a copy of the
+ * data at the first call); 8, 16 or 32 pins that width where it divides n1 (a
+ * width that does not is ignored).  The operator does not depend on the width;
+ * the (r, z) partials of the fused PCG are summed per work-group and may round
+ * differently.  PBR_EINVAL for a NULL context or any other value. */
+pbr_status pbr_set_solve_width(pbr_ctx *c, int bi);
+
 /* Override the constant reference material of the preconditioner
  * (K(m) = Bhat(m) C_ref Bhat(m)^H + shift * rho_ref * I_3, Sec. 5.3-5.4): C21_ref
  * is 21 host doubles in the C21 order, rho_ref > 0. */

@@ -374,6 +374,19 @@ pbr_status pbr_set_stencil_shape(pbr_ctx* c, int ti, int tj) {
   return PBR_OK;
 }
 
+pbr_status pbr_set_solve_width(pbr_ctx* c, int bi) {
+  if (!c) return PBR_EINVAL;
+  if (bi != 0 && bi != 8 && bi != 16 && bi != 32) {
+    c->set_error("mode-solve width must be 0 (autotuned), 8, 16 or 32");
+    return PBR_EINVAL;
+  }
+  if (c->pin_bi != bi) {
+    c->pin_bi = bi;
+    ++c->mat_gen;  // captured PCG graphs hold the old launch shape
+  }
+  return PBR_OK;
+}
+
 pbr_status pbr_set_precond_passes(pbr_ctx* c, int passes) {
   if (!c) return PBR_EINVAL;
   if (passes != 0 && passes != 3 && passes != 5) {

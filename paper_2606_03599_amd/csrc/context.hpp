@@ -104,6 +104,7 @@ struct pbr_ctx {
   int solve_tune_next = 0;
   int pin_ti = 0, pin_tj = 0;  // stencil tile shape pinned by pbr_set_stencil_shape (0: tuned)
   int precond_passes = 0;      // pbr_set_precond_passes: 0 automatic, 3 or 5
+  int pin_bi = 0;              // mode-solve i-width pinned by pbr_set_solve_width (0: tuned)
   hipStream_t stream = nullptr;
   bool own_stream = false;
 

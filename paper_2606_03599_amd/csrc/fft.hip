@@ -974,17 +974,20 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
 // plane pass), folds each orbit pair, solves the two 3x3 systems of its
 // symbols, unfolds, transforms back and writes in place.  Also finishes |r|^2 and the convergence test (rr_in) and
 // writes the (r, z) partials, like fft_solve_kernel.
-constexpr int SOLVE_THREADS = 512;
-// (i-values per work-group: 16 or 32 by the LDS the instance holds, bi <= that
-// at run time; tuned_solve_width picks it.  At n = 128 on the path 16 (50 KB of
-// LDS, three work-groups per CU) measured 4 % faster than 32 (100 KB, one per CU).)
+// Instances: BIM = 8 with 256 threads (26 KB of LDS at L3 = 64, so four
+// work-groups of four waves share a CU and one's loads overlap another's
+// transforms), BIM = 16 and 32 with 512 threads; a launch uses bi <= BIM
+// i-values per work-group, picked per (box, batch size) by tuned_solve_width.
+// The register count (about 124 VGPRs at L3 = 64, set by the 3 x 3 adjugate
+// solves) allows four waves per SIMD, so LDS and work-group size, not
+// registers, decide how many work-groups a CU holds.
 
-template <int L3T, int BIM>
-__global__ void __launch_bounds__(SOLVE_THREADS) solve_plane_kernel(SolveArgs S, int bi) {
+template <int L3T, int BIM, int NT>
+__global__ void __launch_bounds__(NT) solve_plane_kernel(SolveArgs S, int bi) {
   constexpr int PT = L3T + 1;  // LDS pitch of a line along r
   __shared__ cplx sm[3 * BIM * PT];
-  __shared__ cplx roots_s[L3T], e3_s[L3T], e1_s[BIM / 2];
-  __shared__ double red[SOLVE_THREADS / 64 + 1];
+  __shared__ cplx roots_s[L3T], e3_s[L3T], tw_s[L3T], e1_s[BIM / 2];
+  __shared__ double red[NT / 64 + 1];
   long lin;  // XCD-aware numbering of (tile, layout), as in fft_solve_kernel
   {
     const long T = (long)gridDim.x, g = blockIdx.x, x = g % 8, j = g / 8;
@@ -1000,22 +1003,26 @@ __global__ void __launch_bounds__(SOLVE_THREADS) solve_plane_kernel(SolveArgs S,
   const int i0 = (tile % groups_i) * bi;
   const long kstride = (long)S.L1 * S.L2;
   const long base = i0 + (long)S.L1 * q;
-  const int nel = 3 * bi * L3T;
-  constexpr int PER = (3 * BIM * L3T + SOLVE_THREADS - 1) / SOLVE_THREADS;
+  constexpr int PER = (3 * BIM * L3T + NT - 1) / NT;
   const cplx* __restrict__ twist_g = S.b[lay].twist;
+  // element e = threadIdx.x + k NT of the (comp, r, di) box, di fastest: NT is
+  // a multiple of bi (both powers of two), so di is the same for all k of a
+  // thread and (comp, r) = e / bi advances by NT / bi (one division per thread)
+  const int di = threadIdx.x % bi, rest0 = threadIdx.x / bi, rstep = NT / bi;
   cplx v[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int e = threadIdx.x + k * SOLVE_THREADS;
+    const int rest = rest0 + k * rstep;
     v[k] = mk(0, 0);
-    if (e < nel) {
-      const int di = e % bi, rest = e / bi, r = rest % L3T, comp = rest / L3T;
+    if (rest < 3 * L3T) {
+      const int r = rest % L3T, comp = rest / L3T;
       v[k] = data[comp * S.N + base + di + r * kstride];
     }
   }
   for (int t = threadIdx.x; t < L3T; t += blockDim.x) {
     roots_s[t] = S.roots[t];
     e3_s[t] = S.b[lay].e3[t];
+    tw_s[t] = twist_g[t];
   }
   for (int t = threadIdx.x; t < bi / 2; t += blockDim.x) e1_s[t] = S.b[lay].e1[(i0 >> 1) + t];
   if (st && st->done) return;  // uniform per work-group
@@ -1034,12 +1041,13 @@ __global__ void __launch_bounds__(SOLVE_THREADS) solve_plane_kernel(SolveArgs S,
     }
     if (conv) return;  // uniform per work-group
   }
+  __syncthreads();  // the tables
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int e = threadIdx.x + k * SOLVE_THREADS;
-    if (e < nel) {
-      const int di = e % bi, rest = e / bi, r = rest % L3T, comp = rest / L3T;
-      sm[(comp * bi + di) * PT + r] = cmul(v[k], twist_g[r]);
+    const int rest = rest0 + k * rstep;
+    if (rest < 3 * L3T) {
+      const int r = rest % L3T, comp = rest / L3T;
+      sm[(comp * bi + di) * PT + r] = cmul(v[k], tw_s[r]);
     }
   }
   __syncthreads();
@@ -1060,30 +1068,34 @@ __global__ void __launch_bounds__(SOLVE_THREADS) solve_plane_kernel(SolveArgs S,
     const cplx T0 = cmul(o20 ? cb : one, o30 ? cg : one);
     const cplx T1 = cmul(o20 ? one : cb, o30 ? one : cg);
     const cplx t1e = cmulc(Ea, T1);  // T1 e^{-i alpha}
-    cplx c0[3], c1[3], z0[3], z1[3];
+    // m1 = m1' and m1 = m1' + n1/2 (alpha + pi: -Ea) share the half symbols.
+    // The two 3x3 solves run one after the other, each from right-hand sides
+    // read from LDS (the inputs stay there until the pair's outputs replace
+    // them), so only the first solution is live across the second solve.
+    cplx c[3], z0[3], z[3], e[3], h[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const cplx v0 = cmul(T0, sm[(a * bi + 2 * dp) * PT + r]);
-      const cplx v1 = cmul(t1e, sm[(a * bi + 2 * dp + 1) * PT + r]);
-      c0[a] = cadd(v0, v1);
-      c1[a] = csub(v0, v1);
-    }
-    // m1 = m1' and m1 = m1' + n1/2 (alpha + pi: -Ea) share the half symbols
-    cplx h[3], ep[3], em[3];
+    for (int a = 0; a < 3; ++a)
+      c[a] = cadd(cmul(T0, sm[(a * bi + 2 * dp) * PT + r]),
+                  cmul(t1e, sm[(a * bi + 2 * dp + 1) * PT + r]));
     mode_half_symbols(S, Ea, Eb, Eg, h);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      ep[m] = mk(S.cf[m][0] + h[m].x, h[m].y);
-      em[m] = mk(S.cf[m][0] - h[m].x, -h[m].y);
-    }
-    symbol_solve(S, ep, c0, z0);
-    symbol_solve(S, em, c1, z1);
+    for (int m = 0; m < 3; ++m) e[m] = mk(S.cf[m][0] + h[m].x, h[m].y);
+    symbol_solve(S, e, c, z0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rz = fma(c[a].x, z0[a].x, fma(c[a].y, z0[a].y, rz));
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      c[a] = csub(cmul(T0, sm[(a * bi + 2 * dp) * PT + r]),
+                  cmul(t1e, sm[(a * bi + 2 * dp + 1) * PT + r]));
+    mode_half_symbols(S, Ea, Eb, Eg, h);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) e[m] = mk(S.cf[m][0] - h[m].x, -h[m].y);
+    symbol_solve(S, e, c, z);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      rz = fma(c0[a].x, z0[a].x, fma(c0[a].y, z0[a].y, rz));
-      rz = fma(c1[a].x, z1[a].x, fma(c1[a].y, z1[a].y, rz));
-      sm[(a * bi + 2 * dp) * PT + r] = cmulc(T0, cadd(z0[a], z1[a]));
-      sm[(a * bi + 2 * dp + 1) * PT + r] = cmulc(t1e, csub(z0[a], z1[a]));
+      rz = fma(c[a].x, z[a].x, fma(c[a].y, z[a].y, rz));
+      sm[(a * bi + 2 * dp) * PT + r] = cmulc(T0, cadd(z0[a], z[a]));
+      sm[(a * bi + 2 * dp + 1) * PT + r] = cmulc(t1e, csub(z0[a], z[a]));
     }
   }
   if (double* part_out = S.b[lay].part_out) {
@@ -1097,11 +1109,11 @@ __global__ void __launch_bounds__(SOLVE_THREADS) solve_plane_kernel(SolveArgs S,
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int e = threadIdx.x + k * SOLVE_THREADS;
-    if (e < nel) {
-      const int di = e % bi, rest = e / bi, r = rest % L3T, comp = rest / L3T;
+    const int rest = rest0 + k * rstep;
+    if (rest < 3 * L3T) {
+      const int r = rest % L3T, comp = rest / L3T;
       data[comp * S.N + base + di + r * kstride] =
-          cmul(sm[(comp * bi + di) * PT + r], cconj(twist_g[r]));
+          cmul(sm[(comp * bi + di) * PT + r], cconj(tw_s[r]));
     }
   }
 }
@@ -1365,20 +1377,33 @@ struct SolveIO {
   int init = 0;
 };
 
-typedef void (*PlaneSolveKernel)(SolveArgs, int);
+struct PlaneSolveKernel {
+  void (*fn)(SolveArgs, int) = nullptr;
+  int threads = 0;
+};
 
 // Mode-solve kernel of the three-pass structure for third-axis length L3 and
-// i-width bi: the instance whose LDS holds bi (16 or 32 i-values).
+// i-width bi: the smallest instance whose LDS holds bi (8, 16 or 32 i-values)
+// and its work-group size.
 PlaneSolveKernel solve_plane_for(int L3, int bi) {
+  PlaneSolveKernel k;
   switch (L3) {
 #define PBR_CASE(n)                                                           \
   case n:                                                                     \
-    return bi <= 16 ? solve_plane_kernel<n, 16> : solve_plane_kernel<n, 32>;
+    if (bi <= 8) {                                                            \
+      k.fn = solve_plane_kernel<n, 8, 256>;                                   \
+      k.threads = 256;                                                        \
+    } else {                                                                  \
+      k.fn = bi <= 16 ? solve_plane_kernel<n, 16, 512> : solve_plane_kernel<n, 32, 512>; \
+      k.threads = 512;                                                        \
+    }                                                                         \
+    break;
     PBR_PLANE_LENGTHS(PBR_CASE)
 #undef PBR_CASE
     default:
-      return nullptr;
+      break;
   }
+  return k;
 }
 
 // i-width of the mode-solve pass for this box and batch size: the cost model's
@@ -1386,9 +1411,15 @@ PlaneSolveKernel solve_plane_for(int L3, int bi) {
 // third axes up to 32) unless another candidate (8, 16, 32 dividing n1) is at
 // least 5 % faster when timed on a copy of the batch's data at the first call
 // (the pass works in place; the copy is refreshed before each timed launch).
+// Widths 8 run on 256-thread work-groups, 16 and 32 on 512-thread ones.  A
+// width pinned by pbr_set_solve_width that divides n1 replaces all this.
 // The choice is kept per context, so later launches, and the graphs that
 // capture them, use it; with a 5 % margin it is the same from run to run.
 int tuned_solve_width(pbr_ctx* c, const SolveArgs& S, int nb, bool may_tune, int* bi_out) {
+  if (c->pin_bi > 0 && S.L1 % c->pin_bi == 0) {  // pinned by pbr_set_solve_width
+    *bi_out = c->pin_bi;
+    return ST_OK;
+  }
   for (const auto& e : c->solve_tune)
     if (e.nb == nb && e.L1 == S.L1 && e.L2 == S.L2 && e.L3 == S.L3 && e.bi > 0) {
       *bi_out = e.bi;
@@ -1430,9 +1461,11 @@ int tuned_solve_width(pbr_ctx* c, const SolveArgs& S, int nb, bool may_tune, int
                                 hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
           const long nwg = (long)(S.L1 / cand[k]) * S.L2;
           ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
+          const PlaneSolveKernel kk = solve_plane_for(S.L3, cand[k]);
+          ok = ok && kk.fn;
           if (ok)
-            hipLaunchKernelGGL(solve_plane_for(S.L3, cand[k]), dim3((unsigned)(nwg * nb)),
-                               dim3(SOLVE_THREADS), 0, c->stream, T, cand[k]);
+            hipLaunchKernelGGL(kk.fn, dim3((unsigned)(nwg * nb)), dim3(kk.threads), 0,
+                               c->stream, T, cand[k]);
           ok = ok && hipGetLastError() == hipSuccess &&
                hipEventRecord(e1, c->stream) == hipSuccess &&
                hipEventSynchronize(e1) == hipSuccess;
@@ -1502,7 +1535,7 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
     int bi = 0;
     PBR_TRY(tuned_solve_width(c, S, nb, may_tune, &bi));
     const PlaneSolveKernel k = solve_plane_for(S.L3, bi);
-    if (!k) {
+    if (!k.fn) {
       c->set_error("no mode-solve pass for this block box");
       return ST_EINVAL;
     }
@@ -1512,7 +1545,7 @@ int run_solve(pbr_ctx* c, bool blocked, int nb, const SolveIO* io, double shift,
       c->set_error("grid too large for the PCG partial buffers");
       return ST_EINVAL;
     }
-    hipLaunchKernelGGL(k, dim3((unsigned)(nwg * nb)), dim3(SOLVE_THREADS), 0, c->stream, S, bi);
+    hipLaunchKernelGGL(k.fn, dim3((unsigned)(nwg * nb)), dim3(k.threads), 0, c->stream, S, bi);
     PBR_HIP(c, hipGetLastError());
     return ST_OK;
   }

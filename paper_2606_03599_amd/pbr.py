@@ -75,6 +75,7 @@ _SIGS = {
     "pbr_set_palette": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pbr_material_palette": (ctypes.c_int, [_vp]),
     "pbr_set_stencil_shape": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "pbr_set_solve_width": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pbr_set_precond_passes": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pbr_default_shift": (ctypes.c_double, [_vp]),
     "pbr_block_dim": (ctypes.c_long, [_vp, ctypes.c_int]),
@@ -247,6 +248,10 @@ def pbr_material_palette(ctx):
 
 def pbr_set_stencil_shape(ctx, ti, tj):
     _check(ctx, lib().pbr_set_stencil_shape(ctx, int(ti), int(tj)))
+
+
+def pbr_set_solve_width(ctx, bi):
+    _check(ctx, lib().pbr_set_solve_width(ctx, int(bi)))
 
 
 def pbr_set_precond_passes(ctx, passes):
@@ -520,6 +525,11 @@ class Context:
         """Pin the operator kernel's tile shape (16 x 13, or 16 x 11 for the palette
         form); 0, 0 returns the choice to the autotuner."""
         pbr_set_stencil_shape(self.h, ti, tj)
+
+    def set_solve_width(self, bi=0):
+        """Pin the mode-solve pass's i-width (8, 16 or 32); 0 returns it to the
+        autotuner."""
+        pbr_set_solve_width(self.h, bi)
 
     def set_precond_passes(self, passes=0):
         """0 automatic (three passes for a block where available), 3 or 5."""

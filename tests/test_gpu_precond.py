@@ -14,6 +14,7 @@ from synth import complex_gaussian, pack_c21, random_spd_field
 from synth.materials import random_spd_stiffness
 
 from gpu_util import log, make_ctx, rel, to_dev, to_host
+from paper_2606_03599_amd import pbr
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +68,30 @@ def test_block_precond_pass_structures(dims, passes):
             zb_or = F.precond_fft(rb, dims, kap, b, Cref, rref, 1.3)
             zb = to_host(ctx.precond(kap, b, 1.3, to_dev(rb), to_dev(np.zeros_like(rb))))
             assert rel(zb, zb_or) <= TOL, (kap, b)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims", [(32, 32, 16), (64, 64, 8)])
+@pytest.mark.parametrize("width", [8, 16, 32])
+def test_block_precond_solve_widths(dims, width):
+    """The three-pass structure with the mode-solve pass pinned to each i-width
+    (8 on 256-thread work-groups, 16 and 32 on 512-thread ones) matches the
+    oracle at a generic wave vector and at Gamma."""
+    log(f"block precond dims={dims} solve width {width}")
+    C21, rho = random_spd_field(dims, seed=13)
+    n = int(np.prod(dims))
+    ctx = make_ctx(dims, C21, rho)
+    ctx.set_precond_passes(3)
+    ctx.set_solve_width(width)
+    Cref, rref = F.reference_material(C21, rho)
+    for kap in (KAPPA, (0.0, 0.0, 0.0)):
+        for b in range(4):
+            rb = complex_gaussian(3 * n // 4, seed=70 + b)
+            zb_or = F.precond_fft(rb, dims, kap, b, Cref, rref, 0.7)
+            zb = to_host(ctx.precond(kap, b, 0.7, to_dev(rb), to_dev(np.zeros_like(rb))))
+            assert rel(zb, zb_or) <= TOL, (kap, b)
+    with pytest.raises(pbr.PbrError):
+        ctx.set_solve_width(12)
     ctx.close()
 
 

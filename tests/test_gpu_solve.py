@@ -40,13 +40,16 @@ def test_pcg_matches_direct_n8(kappa, precond, passes):
     ctx.close()
 
 
-@pytest.mark.parametrize("passes", [0, 5])
-def test_pcg_residual_n64_block(passes):
+@pytest.mark.parametrize("passes,width", [(0, 0), (0, 8), (0, 16), (0, 32), (5, 0)])
+def test_pcg_residual_n64_block(passes, width):
+    """Fused block PCG at n=64 with each preconditioner pass structure and each
+    pinned mode-solve width (0: autotuned): residual of the oracle's operator."""
     dims = (64, 64, 64)
-    log(f"pcg n=64 block residual, preconditioner passes {passes}")
+    log(f"pcg n=64 block residual, preconditioner passes {passes}, solve width {width}")
     C21, rho, _ = two_phase_cell(dims, radius=0.35, seed=0)
     ctx = make_ctx(dims, C21, rho)
     ctx.set_precond_passes(passes)
+    ctx.set_solve_width(width)
     delta = D.default_shift(C21)
     b = complex_gaussian(3 * 64 ** 3, seed=5)
     bb = Bk.gather(b, dims, 2)
