@@ -98,6 +98,13 @@ def parse():
     p.add_argument("--kernel-stats", metavar="TRACE_DIR",
                    help="print a markdown summary of a rocprofv3 --kernel-trace --stats "
                         "--output-format csv directory: per kernel and per launch grid")
+    p.add_argument("--counter-stats", nargs="+", metavar="PMC_DIR",
+                   help="print the mean of each hardware counter per (kernel, launch grid) "
+                        "from rocprofv3 --pmc --output-format csv directories")
+    p.add_argument("--pcg-probe", action="store_true",
+                   help="a short lockstep PCG workload for hardware-counter runs: the bench "
+                        "cell, one merged solve at the second path point with a 6-vector "
+                        "Krylov space and one outer iteration (it stops unconverged)")
     p.add_argument("--serial-blocks", action="store_true",
                    help="solve the four blocks one after another instead of in lockstep")
     return p.parse_args()
@@ -257,6 +264,59 @@ def kernel_stats(trace_dir, top=16):
     for k, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
         out.append(f"| {k[0]} | ({k[1]}, {k[2]}, {k[3]}) | {k[4]} | {c} | {t / c:.1f} |")
     return "\n".join(out)
+
+
+def counter_stats(dirs):
+    """Mean value of each hardware counter per (kernel, launch grid, work-group)
+    over the dispatches of rocprofv3 --pmc csv runs, one markdown table per run."""
+    import collections
+    import csv
+    import glob
+    out = []
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(files[0])):
+            nm = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+            nm = nm[:nm.index(">") + 1] if "<" in nm else nm.split("(")[0]
+            agg[(nm, r.get("Grid_Size", ""), r.get("Workgroup_Size", ""))][r["Counter_Name"]].append(
+                float(r["Counter_Value"]))
+        names = sorted({c for v in agg.values() for c in v})
+        out.append(f"{os.path.basename(os.path.normpath(d))}:\n")
+        out.append("| kernel | grid | work-group | dispatches | " + " | ".join(names) + " |")
+        out.append("|---" * (4 + len(names)) + "|")
+        for key, cs in sorted(agg.items()):
+            n = max(len(v) for v in cs.values())
+            vals = [f"{sum(cs[c]) / len(cs[c]):.4g}" if cs.get(c) else "" for c in names]
+            out.append(f"| {key[0]} | {key[1]} | {key[2]} | {n} | " + " | ".join(vals) + " |")
+        out.append("")
+    return "\n".join(out)
+
+
+def pcg_probe(n=128):
+    """Short lockstep PCG workload (hardware-counter runs): the bench cell, one
+    merged solve at the second path point with a 6-vector Krylov space and a
+    single outer iteration, which stops unconverged after a few thousand
+    four-layout PCG launches."""
+    import torch
+    from paper_2606_03599_amd import pbr
+    from synth import sc_path, two_phase_cell
+    C21, rho, _ = two_phase_cell((n, n, n), radius=0.35, seed=0)
+    ctx = pbr.Context((n, n, n))
+    ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
+    del C21, rho
+    kappas, _ = sc_path(16)
+    o = pbr.pbr_opts_default()
+    o.ncv = 6
+    o.maxit_outer = 1
+    try:
+        ctx.eigs_merged(tuple(kappas[1]), 4, opts=o)
+    except pbr.PbrError as e:
+        log(f"pcg probe stopped as set up (status {e.status})")
+    torch.cuda.synchronize()
+    ctx.close()
 
 
 def traffic_record(kernel_src, name):
@@ -552,6 +612,12 @@ def main():
         print(json.dumps({"error": "this build measures one GPU: collectives and sharding are "
                                    "not part of it, so --gpus must be 1"}))
         sys.exit(2)
+    if args.counter_stats:
+        print(counter_stats(args.counter_stats), flush=True)
+        return
+    if args.pcg_probe:
+        pcg_probe(args.n if args.n > 0 else 128)
+        return
     if args.kernel_stats:
         print(kernel_stats(args.kernel_stats), flush=True)
         return
