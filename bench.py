@@ -71,7 +71,7 @@ def parse():
     p.add_argument("--group", type=int, default=4,
                    help="path points per step (solved in lockstep; 4 = the blocked "
                         "path's own batch)")
-    p.add_argument("--study", choices=("refinement", "cells", "gap"), default=None,
+    p.add_argument("--study", choices=("refinement", "cells", "gap", "path"), default=None,
                    help="refinement: grouped grid-refinement errors of the FCC workload at "
                         "Gamma, X and W against a 256^3 reference (Sec. 7.5; one JSON line)")
     p.add_argument("--workload", choices=("cube", "fcc"), default="cube",
@@ -80,6 +80,9 @@ def parse():
     p.add_argument("--n", type=int, default=0, help="grid size (default 128 cube, 60 fcc)")
     p.add_argument("--nk", type=int, default=16, help="path points (cube workload)")
     p.add_argument("--nev", type=int, default=0, help="eigenpairs per k (default 20 cube, 40 fcc)")
+    p.add_argument("--range", nargs=2, type=int, metavar=("FROM", "TO"), default=None,
+                   help="--study path: solve path points FROM <= i < TO only (a long path in "
+                        "several runs)")
     p.add_argument("--first", type=int, default=0,
                    help="time only the first m points of the path (short profiled runs)")
     p.add_argument("--full-every", type=int, default=4,
@@ -549,6 +552,56 @@ def gap_gradient_study(n, nev, points=("X", "R"), seed=0):
                                   "rel_diff": abs(ana - fd) / max(abs(fd), 1e-300)}}
 
 
+def path_study(n, nk, nev, rng_pts=None, group=2, seed=0):
+    """Blocked band path of the two-phase cell (radius 0.35) at n^3 over the
+    nk-point Gamma-X-M-Gamma-R path, nev eigenpairs per k, tolerances 1e-12:
+    points FROM <= i < TO (all by default), solved `group` points at a time in
+    lockstep (four blocks each), each group logged as it ends."""
+    import torch
+    from paper_2606_03599_amd import pbr
+    from synth import sc_path, two_phase_cell
+    kappas, _ = sc_path(nk)
+    a, b = (0, nk) if rng_pts is None else (max(0, rng_pts[0]), min(nk, rng_pts[1]))
+    dims = (n, n, n)
+    t_setup = time.perf_counter()
+    C21, rho = two_phase_cell(dims, radius=0.35, seed=seed)[:2]
+    ctx = pbr.Context(dims)
+    ctx.set_material(torch.from_numpy(C21).cuda(), torch.from_numpy(rho).cuda())
+    del C21, rho
+    torch.cuda.synchronize()
+    log(f"n={n}: material set in {time.perf_counter() - t_setup:.1f} s; points {a}..{b - 1} of "
+        f"{nk}, {nev} eigenpairs, {group} points per group")
+    total = 0.0
+    solves = pcg_sum = 0
+    max_resid = 0.0
+    groups, evals = [], {}
+    for g0 in range(a, b, group):
+        ks = kappas[g0:min(g0 + group, b)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, st = ctx.band_path(ks, nev)
+        dt = time.perf_counter() - t0
+        total += dt
+        solves += st.op_applies
+        pcg_sum += st.pcg_iters_total
+        max_resid = max(max_resid, st.max_rel_resid)
+        groups.append({"points": [g0, g0 + len(ks) - 1], "s": round(dt, 3),
+                       "solves": st.op_applies, "pcg_avg": round(st.pcg_avg, 2)})
+        for q in range(len(ks)):
+            evals[g0 + q] = [float(x) for x in ev[q]]
+        log(f"points {g0}-{g0 + len(ks) - 1}: {dt:.1f} s, {st.op_applies} solves, "
+            f"{st.pcg_avg:.1f} PCG per solve (total {total:.1f} s)")
+    ctx.close()
+    return {"study": "blocked band path of the two-phase cube, run in ranges of path points",
+            "workload": f"two-phase unit cube n={n}^3 ({n ** 3} nodes, four blocks of "
+                        f"{n ** 3 // 4}), {nk}-point Gamma-X-M-Gamma-R path, {nev} lowest "
+                        f"eigenpairs per k, tolerances 1e-12",
+            "n": n, "nk": nk, "nev": nev, "range": [a, b], "group": group,
+            "path_s": round(total, 3), "s_per_point": round(total / max(1, b - a), 3),
+            "solves": solves, "pcg_avg": round(pcg_sum / max(1, solves), 2),
+            "max_rel_resid": max_resid, "groups": groups, "eigenvalues": evals}
+
+
 def cells_study(nk, nev, count=8, seed=0, first=0):
     """Uneven batch of two-phase cells (n drawn from {64, 96, 128}, inclusion
     radius from U[0.2, 0.4], each with its own seeded inclusion stiffness): the
@@ -630,6 +683,12 @@ def main():
     if args.study == "gap":
         print(json.dumps(gap_gradient_study(args.n if args.n > 0 else 256,
                                             args.nev if args.nev > 0 else 30)), flush=True)
+        return
+    if args.study == "path":
+        print(json.dumps(path_study(args.n if args.n > 0 else 256, args.nk,
+                                    args.nev if args.nev > 0 else 30, args.range,
+                                    max(1, min(4, args.group)))),
+              flush=True)
         return
     if args.study == "cells":
         print(json.dumps(cells_study(args.nk if args.nk != 16 else 24,
