@@ -209,7 +209,13 @@ pbr_status pbr_block_scatter(pbr_ctx *c, int block, const void *blk, void *full,
 
 /* y = (A_h(k) + s M_h) x in the full space (block = -1) or restricted to a
  * parity block (A_sigma + s M_sigma, Eq. 4.14), matrix-free as
- * x -> B^H x -> C B^H x -> B C B^H x (Sec. 6.1).  x and y must not overlap. */
+ * x -> B^H x -> C B^H x -> B C B^H x (Sec. 6.1).  x and y must not overlap.
+ * Size limit (32-bit buffer offsets in the kernel): one layout's vector (48 B
+ * per node) and its stiffness tiles (176 B per node, runs of 16 nodes along n1)
+ * must each stay below 2 GiB: a cube up to n = 225 in the full space and up to
+ * n = 364 in the parity blocks (a block holds a quarter of the nodes); larger
+ * grids get PBR_EINVAL from this call and from every call that applies the
+ * operator (pbr_apply_blocks, pbr_solve, the eigensolvers, pbr_eig_grad). */
 pbr_status pbr_apply(pbr_ctx *c, const double kappa[3], int block, double s,
                      const void *x, void *y, int on_device);
 
@@ -313,7 +319,12 @@ pbr_status pbr_band_path(pbr_ctx *c, int nk, const double *kappas, int nev,
  * host); shift <= 0 takes each cell's default.  The cells' paths run
  * concurrently, one native host thread per cell driving its context's own
  * stream, so that small cells fill the GPU together; every cell's eigenvalues
- * are bit for bit those of pbr_band_path on it.  The contexts must be distinct,
+ * are bit for bit those of pbr_band_path on it in the same state.  (A context's
+ * autotuners pick the operator's tile shape and the mode-solve width by timing
+ * at its first launch of each shape of batch, and those choices group the PCG
+ * inner products; first calls timed under different load can choose
+ * differently.  pbr_set_stencil_shape and pbr_set_solve_width pin them.)  The
+ * contexts must be distinct,
  * on one device, and must not share a stream; 1 <= ncells <= 64.  st (optional)
  * receives ncells statistics.  Returns PBR_OK, or the first failing cell's
  * status (its message via pbr_last_error on that context; every cell is run);
