@@ -253,11 +253,21 @@ def test_merged_resolve_reproducible():
     a context that has run it before, and on a second fresh context: the second
     solve of the block starts from that block's own Ritz vectors every time (its
     Krylov basis grows on the first call and keeps them).  The values also match
-    the full-space solve (Corollary 4.2)."""
+    the full-space solve (Corollary 4.2).  Both contexts pin the operator's tile
+    shape and the mode-solve width: left to the autotuners, two fresh contexts
+    may time their candidates differently and group the PCG inner products
+    differently."""
     dims = (32, 32, 32)
     C21, rho, _ = two_phase_cell(dims, radius=0.2, seed=0)
     G = (0.0, 0.0, 0.0)
-    ctx = make_ctx(dims, C21, rho)
+
+    def pinned_ctx():
+        c = make_ctx(dims, C21, rho)
+        c.set_stencil_shape(16, 11)
+        c.set_solve_width(16)
+        return c
+
+    ctx = pinned_ctx()
     log("eigs_merged n=32 Gamma nev=20, twice on one context")
     e1, s1 = ctx.eigs_merged(G, 20)
     e2, s2 = ctx.eigs_merged(G, 20)
@@ -268,7 +278,7 @@ def test_merged_resolve_reproducible():
     ef, sf, _ = ctx.eigs(G, -1, 20)
     assert np.all(np.abs(e1 - ef) <= TOL * np.abs(ef)), (e1, ef)
     ctx.close()
-    ctx = make_ctx(dims, C21, rho)
+    ctx = pinned_ctx()
     log("eigs_merged n=32 Gamma nev=20 on a second context")
     e3, _ = ctx.eigs_merged(G, 20)
     assert np.array_equal(e1, e3), rel(e1, e3)
