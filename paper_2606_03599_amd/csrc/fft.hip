@@ -441,7 +441,12 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_lines_kernel(LineArgs A) {
 // Scalars: alpha uses rz_next (the previous last pass's (r, z)); the first
 // work-group of the first pass moves it to rz, which the last pass divides by.
 // ---------------------------------------------------------------------------
-constexpr int PLANE_THREADS = 512;
+// Work-group size of a plane pass: one work-group holds a whole plane (133 KB
+// of LDS at n = 128), so it is alone on its CU and its transform phase issues
+// no memory traffic; 1024 threads (16 waves) shorten that phase.  The inverse
+// pass holds z, the old p and x in registers and keeps 512 threads: at 1024
+// (a 128-register bound) it spills.
+constexpr int plane_threads(int mode) { return mode == 2 ? 512 : 1024; }
 
 struct PlaneArgs {
   int L3;            // planes (y3 extent)
@@ -542,7 +547,8 @@ __device__ inline void plane_axis(cplx* sm, const cplx* __restrict__ roots) {
 }
 
 template <int L0, int L1, int SIGN, int MODE>
-__global__ void __launch_bounds__(PLANE_THREADS) plane_kernel(PlaneArgs A) {
+__global__ void __launch_bounds__(plane_threads(MODE)) plane_kernel(PlaneArgs A) {
+  constexpr int PLANE_THREADS = plane_threads(MODE);
   constexpr int NEL = 2 * L0 * L1;  // plane elements, both sub-lattices
   constexpr int N1 = 2 * L0;        // i extent of the block box
   constexpr int RP = L0 + 1, SP = plane_sp(L0, L1);
@@ -1334,10 +1340,12 @@ int run_plane(pbr_ctx* c, int nb, int sign, int mode, const PlaneIO* io, double 
               long part_cap, int* nparts) {
   const int L0 = c->n1 / 2, L1 = c->n2 / 2, L3 = c->n3 / 2;
   PlaneKernel k = nullptr;
+  // MODE of the instance chosen (its work-group size follows from it)
+  const int kmode = sign < 0 ? (mode == 1 ? 1 : 0) : (mode == 2 ? 2 : 0);
   if (sign < 0)
-    k = mode == 1 ? plane_kernel_for<-1, 1>(L0, L1) : plane_kernel_for<-1, 0>(L0, L1);
+    k = kmode == 1 ? plane_kernel_for<-1, 1>(L0, L1) : plane_kernel_for<-1, 0>(L0, L1);
   else
-    k = mode == 2 ? plane_kernel_for<1, 2>(L0, L1) : plane_kernel_for<1, 0>(L0, L1);
+    k = kmode == 2 ? plane_kernel_for<1, 2>(L0, L1) : plane_kernel_for<1, 0>(L0, L1);
   if (!k) {
     c->set_error("no plane pass for this block box");
     return ST_EINVAL;
@@ -1360,7 +1368,7 @@ int run_plane(pbr_ctx* c, int nb, int sign, int mode, const PlaneIO* io, double 
     c->set_error("grid too large for the PCG partial buffers");
     return ST_EINVAL;
   }
-  hipLaunchKernelGGL(k, dim3(L3, 3, nb), dim3(PLANE_THREADS), 0, c->stream, A);
+  hipLaunchKernelGGL(k, dim3(L3, 3, nb), dim3(plane_threads(kmode)), 0, c->stream, A);
   PBR_HIP(c, hipGetLastError());
   return ST_OK;
 }
