@@ -984,9 +984,9 @@ __global__ void __launch_bounds__(FFT_THREADS) fft_solve_kernel(SolveArgs S) {
 // work-groups of four waves share a CU and one's loads overlap another's
 // transforms), BIM = 16 and 32 with 512 threads; a launch uses bi <= BIM
 // i-values per work-group, picked per (box, batch size) by tuned_solve_width.
-// The register count (about 124 VGPRs at L3 = 64, set by the 3 x 3 adjugate
-// solves) allows four waves per SIMD, so LDS and work-group size, not
-// registers, decide how many work-groups a CU holds.
+// The register count (124-128 VGPRs at L3 = 64, set by the 3 x 3 adjugate
+// solves) allows four waves per SIMD: two 512-thread work-groups per CU (their
+// LDS would allow three) or four 256-thread ones.
 
 template <int L3T, int BIM, int NT>
 __global__ void __launch_bounds__(NT) solve_plane_kernel(SolveArgs S, int bi) {
@@ -1422,7 +1422,11 @@ PlaneSolveKernel solve_plane_for(int L3, int bi) {
 // Widths 8 run on 256-thread work-groups, 16 and 32 on 512-thread ones.  A
 // width pinned by pbr_set_solve_width that divides n1 replaces all this.
 // The choice is kept per context, so later launches, and the graphs that
-// capture them, use it; with a 5 % margin it is the same from run to run.
+// capture them, use it.  The 5 % margin keeps it stable where one width is
+// clearly faster; where two time within noise of each other (four layouts at
+// n = 128: 8 and 16) fresh contexts may choose differently, and with the width
+// the grouping of the (r, z) partials, so the last bits of a solve.
+// pbr_set_solve_width pins the width where that matters.
 int tuned_solve_width(pbr_ctx* c, const SolveArgs& S, int nb, bool may_tune, int* bi_out) {
   if (c->pin_bi > 0 && S.L1 % c->pin_bi == 0) {  // pinned by pbr_set_solve_width
     *bi_out = c->pin_bi;
