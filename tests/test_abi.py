@@ -64,6 +64,8 @@ def test_null_context_calls_fail_cleanly(L):
     assert L.pbr_material_palette(None) == -1
     assert L.pbr_set_palette(None, 1) == -1  # PBR_EINVAL
     assert L.pbr_set_stencil_shape(None, 16, 13) == -1
+    assert L.pbr_set_solve_width(None, 16) == -1
+    assert L.pbr_set_precond_passes(None, 3) == -1
     L.pbr_destroy(None)
 
 
