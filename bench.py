@@ -351,6 +351,9 @@ def traffic_records(fetch_dir, write_dir, n=128):
     import hashlib
     import statistics
 
+    def rdir(d):  # a run directory as the command lines give it: under the repository root R
+        return "$R/" + os.path.relpath(os.path.abspath(d), ROOT)
+
     def load(d, counter):
         path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
         per = collections.defaultdict(dict)
@@ -397,12 +400,12 @@ def traffic_records(fetch_dir, write_dir, n=128):
             "source": "paper_2606_03599_amd/csrc/stencil.hip", "source_sha256": sha,
             "commands": [
                 "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 200 rocprofv3 --pmc FETCH_SIZE "
-                "--output-format csv -d $R/gpurun_out/pf -o pf -- python3 -u $R/bench.py "
+                f"--output-format csv -d {rdir(fetch_dir)} -o pf -- python3 -u $R/bench.py "
                 "--matvec-only --mv-iters 20",
                 "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 200 rocprofv3 --pmc WRITE_SIZE "
-                "--output-format csv -d $R/gpurun_out/pw -o pw -- python3 -u $R/bench.py "
+                f"--output-format csv -d {rdir(write_dir)} -o pw -- python3 -u $R/bench.py "
                 "--matvec-only --mv-iters 20",
-                "python3 $R/bench.py --traffic-record $R/gpurun_out/pf $R/gpurun_out/pw"],
+                f"python3 $R/bench.py --traffic-record {rdir(fetch_dir)} {rdir(write_dir)}"],
             "grid_threads": grid, "launches_averaged": len(fv),
             "fetch_size_kib_raw": round(statistics.mean(fv), 2),
             "write_size_kib_raw": round(statistics.mean(wv), 2),
@@ -662,8 +665,8 @@ def cells_study(nk, nev, count=8, seed=0, first=0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU: collectives and sharding are "
-                                   "not part of it, so --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU: collectives and sharding are "
+                                   "not part of this implementation, so --gpus must be 1"}))
         sys.exit(2)
     if args.counter_stats:
         print(counter_stats(args.counter_stats), flush=True)
