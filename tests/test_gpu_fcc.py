@@ -38,22 +38,28 @@ def test_fcc_merged_and_full_vs_oracle(dims, point):
 
 def test_fcc_n128_matches_paper_frequencies():
     """The paper's printed 128^3 results (four-band group averages, Sec. 7.3)
-    at Gamma, X, W and L.  The paper does not say how the silicon volume fraction
-    of a cut cell is computed (here: 4^3 sub-samples), and prints 5 digits, so
-    agreement is expected only to ~1e-3."""
+    at Gamma, X, W and L, 5 significant digits (relative rounding 2-4e-5).
+    With the material sampled at the nodes (no smoothing) the computed groups
+    agree with them to 1.5e-6 - 4.7e-5, about the printed precision, which
+    pins the operator, the lattice, the wave vectors, the constants and the
+    frequency scale; the reading's volume-fraction material (4^3 sub-samples
+    per cut cell, Sec. 7.1) moves the groups by 1.4-2.4e-4 -- the paper's own
+    cut-cell rule evidently moves them less, and it does not say how it
+    computes the fraction."""
     import json
     import os
     from synth import frequency_hz
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fcc_paper_table.json")))
     dims = (128, 128, 128)
-    C21, rho, A, _ = fcc_quartz_si_cell(dims, supersample=4)
-    ctx = make_ctx(dims, C21, rho, A)
-    for row in g["rows"]:
-        grp = row["group"] - (g["zero_groups_at_gamma"] if row["point"] == "G" else 0)
-        log(f"fcc n=128 {row['point']} G{row['group']}")
-        ev, st = ctx.eigs_merged(tuple(fcc_point(row["point"])), 4 * grp)
-        f = frequency_hz(ev)[4 * (grp - 1):4 * grp].mean()
-        ref = row["present_result_hz"]
-        log(f"  ours {f:.5e} paper {ref:.4e} rel {(f - ref) / ref:+.2e}")
-        assert abs(f - ref) <= 1e-3 * ref
-    ctx.close()
+    for supersample, tol in ((1, 6e-5), (4, 5e-4)):
+        C21, rho, A, _ = fcc_quartz_si_cell(dims, supersample=supersample)
+        ctx = make_ctx(dims, C21, rho, A)
+        for row in g["rows"]:
+            grp = row["group"] - (g["zero_groups_at_gamma"] if row["point"] == "G" else 0)
+            log(f"fcc n=128 ({supersample}^3 samples) {row['point']} G{row['group']}")
+            ev, st = ctx.eigs_merged(tuple(fcc_point(row["point"])), 4 * grp)
+            f = frequency_hz(ev)[4 * (grp - 1):4 * grp].mean()
+            ref = row["present_result_hz"]
+            log(f"  ours {f:.5e} paper {ref:.4e} rel {(f - ref) / ref:+.2e}")
+            assert abs(f - ref) <= tol * ref, (supersample, row["point"])
+        ctx.close()
